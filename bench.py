@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark: body-steps/s of the bowl pile at projected Gauss-Seidel residual <= 1e-4.
+
+Workload: 20,000 spheres (radius U(0.2, 0.5) m, density 1000 kg/m^3) dropped
+into a five-plane bowl, mu = 0.6, h = 1/60 s, 8 k-means spatial partitions with
+a 2-hop overlap (recomputed every 10 steps), geodesic search depth 4, plain
+warm start, adaptive sweeps to a residual of 1e-4 m/s with a cap of 1000.
+The timed region is the scene's full 1000-step run from its initial state
+(the warm-up steps run first and the state is then reset), rebalancing
+included.
+
+One GPU only.  Prints one JSON line.  The roofline entry is for the
+Gauss-Seidel kernel: algorithmic bytes of all sweeps of the timed steps (per
+sweep and constraint copy: 220 B for two bodies, 164 B with a static body,
+192 B for a joint) over its summed duration from HIP events recorded on the
+stream the kernel runs on.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pgs_traffic.json")
+SOLVER_SRC = os.path.join(ROOT, "paper_2403_17261_amd", "csrc", "solve.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def solver_hash():
+    with open(SOLVER_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per solver launch from committed rocprofv3 counters, if they match this kernel."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("solver_sha") != solver_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def run_loop(w, sc, steps, state0, owner0, cent0, rebalance_iters=3):
+    """steps steps of the scene, rebalancing the k-means owners every sc.rebalance_every steps."""
+    from paper_2403_17261_amd import scenes
+
+    owner, cent = owner0, cent0
+    t = 0
+    every = sc.rebalance_every or steps
+    while t < steps:
+        if t > 0 and t % every == 0 and sc.rebalance_every:
+            st = w.read_state()
+            owner, cent = scenes.kmeans_owner(st[:, :3], int(sc.parts_per_scene[0]), iters=rebalance_iters,
+                                              centroids=cent)
+            w.set_partitions(owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        n = min(every - t % every, steps - t)
+        w.step(n)
+        t += n
+    return owner, cent
+
+
+def cpu_baseline(n_steps, tol, cap):
+    """The oracle (single thread, double precision) on the settled bowl pile written by oracle/pile_state.py."""
+    import oracle
+    from paper_2403_17261_amd import scenes
+
+    path = os.path.join(ROOT, "oracle", "data", "bowl20k_seed0_t300.npz")
+    if not os.path.exists(path):
+        return None
+    d = np.load(path)
+    sc = scenes.config2(0)
+    st, owner = d["state"], d["owner"]
+    kw = dict(adaptive=True, tol=tol, max_iters=cap)
+    o = oracle.step(sc, state=st, owner=owner, **kw)           # untimed: fills the warm-start cache
+    st = o["state"].astype(np.float32)
+    t0 = time.perf_counter()
+    sweeps = 0
+    for _ in range(n_steps):
+        o = oracle.step(sc, state=st, owner=owner, cache=o, **kw)
+        st = o["state"].astype(np.float32)
+        sweeps += int(o["max_iters"])
+    dt = time.perf_counter() - t0
+    return {
+        "value": sc.n_bodies * n_steps / dt, "unit": "body-steps/s", "cores": 1, "kind": "oracle",
+        "sample": f"{n_steps} oracle steps (double precision, one thread, adaptive sweeps to 1e-4, cap {cap}) "
+                  f"of the 20,000-sphere bowl pile from its oracle-computed state at step 300 "
+                  f"(mean {sweeps / n_steps:.0f} sweeps per step, {dt:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--mode", choices=["adaptive", "fixed"], default="adaptive")
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--cap", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU; a run on several GPUs is not provided "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sc = scenes.config2(0)
+    mode = ovl.MODE_ADAPTIVE if args.mode == "adaptive" else ovl.MODE_FIXED
+    cap = args.cap if mode == ovl.MODE_ADAPTIVE else sc.iters
+    p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN)
+    w = ovl.World(sc, p)
+    owner0, cent0 = sc.owner.copy(), sc.centroids[0].copy()
+    w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+    log(f"warm-up: {args.warmup} steps")
+    run_loop(w, sc, args.warmup, sc.state, owner0, cent0)
+    w.sync()
+    # reset to the scene's initial state: the timed steps are the run's first `steps` steps
+    w.write_state(sc.state, keep_cache=False)
+    w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+    w.profile(True)
+    c0 = w.counters()
+    log(f"timed: {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_loop(w, sc, args.steps, sc.state, owner0, cent0)
+    w.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = w.counters()
+    last = w.step(0, stats=True)
+    secs = t1 - t0
+    steps_done = c1["steps"] - c0["steps"]
+    if steps_done != args.steps:
+        raise RuntimeError(f"only {steps_done} of {args.steps} steps committed")
+    pgs_ms = c1["pgs_ms"] - c0["pgs_ms"]
+    pgs_launches = c1["pgs_launches"] - c0["pgs_launches"]
+    pgs_bytes = c1["pgs_bytes"] - c0["pgs_bytes"]
+    achieved = pgs_bytes / (pgs_ms * 1e-3) / 1e9 if pgs_ms > 0 else 0.0
+    traffic = measured_traffic()
+    sweeps_mean = (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / max(1, steps_done)
+    unconv = c1["unconverged_total"] - c0["unconverged_total"]
+    value = sc.n_bodies * args.steps / secs
+    log(f"{value:.3e} body-steps/s, {1e3 * secs / args.steps:.3f} ms/step, solver {pgs_ms / max(1, pgs_launches):.3f} "
+        f"ms/launch, {achieved:.1f} GB/s algorithmic, mean sweeps {sweeps_mean:.1f}, unconverged {unconv}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: {args.cpu_steps} oracle steps")
+        cpu = cpu_baseline(args.cpu_steps, args.tol, args.cap)
+    out = {
+        "metric": "body-steps/s at PGS residual <=1e-4; learned warm-start vs plain PGS",
+        "value": value,
+        "unit": "body-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * secs / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "bowl pile: 20,000 spheres r~U(0.2,0.5) m, density 1000, five-plane bowl, mu 0.6, h 1/60 s, "
+                        "8 k-means partitions (recomputed every 10 steps), 2-hop overlap, beta 4, first "
+                        f"{args.steps} steps from the initial drop",
+            "n_bodies": sc.n_bodies, "partitions": int(sc.parts_per_scene[0]), "halo_k": sc.halo_k,
+            "beta": sc.beta, "sweeps": f"{args.mode}, tol {args.tol}, cap {cap}", "warm_start": "plain",
+            "mean_sweeps_per_step": round(sweeps_mean, 2), "unconverged_partition_steps": int(unconv),
+            "last_step": {k: last[k] for k in ("n_contacts", "n_copies", "n_replicas", "n_overlap",
+                                               "max_colours")},
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_pgs (coloured projected Gauss-Seidel, one workgroup per partition)",
+            "launches": int(pgs_launches), "ms_per_launch": pgs_ms / max(1, pgs_launches),
+            "alg_bytes_per_launch": pgs_bytes / max(1, pgs_launches),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    w.close()
+
+
+if __name__ == "__main__":
+    main()

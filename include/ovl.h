@@ -1,0 +1,252 @@
+/* ovl.h - C ABI of the MI355X overlapping-partition rigid-body stepper.
+ *
+ * The library steps rigid bodies with the overlapping-partition method of
+ * Kale & Kry, "Distributed Simulation of Large Multi-body Systems"
+ * (arXiv 2403.17261).  The paper's workers become independent sub-solves
+ * ("partitions") on one GPU; every step runs, on the device:
+ *   contacts (Alg. 1 getContacts) -> constraint graph (section 5.1) ->
+ *   overlap sets (section 4, Eq. 9-10; Alg. 2-3 read as a k-hop halo) ->
+ *   geodesic weights (section 5.3, Eq. 15-16, Alg. 5) -> per-partition MLCP
+ *   rows (section 3, Eq. 1-7) -> graph colouring -> projected Gauss-Seidel ->
+ *   integration -> blending of the overlap bodies (section 5.2, Eq. 11-14,
+ *   Alg. 4), which also resets every replica for the next step (Alg. 1).
+ *
+ * Conventions
+ *  - All pointers are plain host pointers unless a `*_is_device` flag says
+ *    otherwise.  Input arrays are borrowed for the duration of the call and
+ *    copied; the library never keeps a caller pointer.
+ *  - A body state is 13 float32 in the paper's order (section 4, Eq. 8):
+ *    position x(3), rotation quaternion q(4, scalar first), linear velocity
+ *    v(3), angular velocity w(3), all in the world frame.  State arrays are
+ *    row-major [n_bodies][13].
+ *  - Bodies are sorted by scene id; the scenes of one world never interact.
+ *    Partition ids are global: scene s owns the contiguous range
+ *    [base_s, base_s + parts_per_scene[s]) with base_s the sum of the earlier
+ *    scenes' counts.  A scene has 1..64 partitions.
+ *  - Every call returns an ovl_status; no exception crosses the ABI.  The
+ *    text of the last error of a world is returned by ovl_last_error().
+ *  - A world belongs to one host thread and one HIP stream.
+ */
+#ifndef OVL_H
+#define OVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OVL_OK = 0,
+  OVL_ERR_INVALID_ARG = 1, /* a size, index or flag is out of range */
+  OVL_ERR_OOM = 2,         /* device allocation failed */
+  OVL_ERR_CAPACITY = 3,    /* a per-step buffer overflowed and could not be grown */
+  OVL_ERR_NONFINITE = 4,   /* a step produced NaN/Inf; the state stays at the last good step */
+  OVL_ERR_DEVICE = 5,      /* a HIP call failed */
+  OVL_NOT_CONVERGED = 6    /* informational: some partition hit the iteration cap in adaptive mode */
+} ovl_status;
+
+typedef struct ovl_world ovl_world;
+
+/* Scene content of a world (section 4: the set of non-static bodies plus
+ * static bodies of infinite mass).  Only spheres (shape 0) with isotropic
+ * inertia are accepted by this version. */
+typedef struct {
+  int32_t n_bodies;            /* N >= 0 */
+  int32_t n_scenes;            /* S >= 1 */
+  int32_t n_joints;            /* J >= 0 */
+  const int32_t* scene;        /* [N] scene id, nondecreasing */
+  const int32_t* shape;        /* [N] 0 = sphere */
+  const float* radius;         /* [N] > 0 */
+  const float* halflen;        /* [N] unused for spheres (may be NULL) */
+  const float* mass;           /* [N] > 0 */
+  const float* inertia;        /* [N*3] body-frame principal moments (all three equal) */
+  const float* state;          /* [N*13] initial states */
+  const float* mu;             /* [S] Coulomb friction coefficient (section 3, Eq. 5-7) */
+  const float* margin;         /* [S] contact margin: a pair is in contact when its gap < margin */
+  const int32_t* plane_off;    /* [S+1] planes of scene s: [plane_off[s], plane_off[s+1]) */
+  const float* planes;         /* [P*4] static planes n.x = c (n unit, pointing to the free side) */
+  const int32_t* ssph_off;     /* [S+1] */
+  const float* ssph;           /* [Q*4] static spheres: centre(3), radius */
+  const int32_t* joint_ab;     /* [J*2] ball joints between two bodies of one scene, sorted by scene */
+  const float* joint_anchor;   /* [J*6] body-frame anchor on body a, then on body b */
+} ovl_world_desc;
+
+enum { OVL_MODE_FIXED = 0, OVL_MODE_ADAPTIVE = 1 };
+enum { OVL_WARM_NONE = 0, OVL_WARM_PLAIN = 1 };
+
+/* Step parameters.  Eq. 2's compliance C is cfm * identity; its
+ * stabilisation term is applied as erp * phi / h for penetrations and phi / h
+ * for open gaps.  Adaptive mode stops a partition's Gauss-Seidel sweeps when
+ * the largest |A_rr * delta lambda_r| of a sweep is <= tol (m/s), capped at
+ * max_iters; fixed mode runs exactly max_iters sweeps. */
+typedef struct {
+  float dt;           /* time step h (s) */
+  float gravity[3];   /* m/s^2 */
+  float cfm;          /* >= 0 */
+  float erp;          /* in [0, 1] */
+  float tol;          /* adaptive stop threshold, m/s */
+  int32_t max_iters;  /* >= 1 (cap 100000) */
+  int32_t mode;       /* OVL_MODE_* */
+  int32_t warmstart;  /* OVL_WARM_* */
+  uint32_t seed;      /* colouring priority seed */
+} ovl_params;
+
+/* Device context: the stream every kernel runs on (NULL = the null stream)
+ * and optional allocation callbacks (NULL = hipMalloc/hipFree).  The Python
+ * binding passes PyTorch's current stream and caching allocator. */
+typedef struct {
+  void* stream;                                  /* hipStream_t */
+  void* (*alloc)(size_t bytes, void* user);      /* returns device memory or NULL */
+  void (*free)(void* ptr, void* user);
+  void* user;
+} ovl_device_ctx;
+
+/* Per-call statistics of the last step (totals where marked). */
+typedef struct {
+  int64_t n_contacts;      /* contacts found (Alg. 1 getContacts) */
+  int64_t n_copies;        /* constraint copies summed over partitions */
+  int64_t n_replicas;      /* body replicas summed over partitions */
+  int64_t n_overlap;       /* bodies active in >= 2 partitions (the overlap set O, Eq. 10) */
+  int32_t max_colours;     /* largest colour count of a partition */
+  int32_t max_iters;       /* largest sweep count of a partition */
+  int32_t n_unconverged;   /* partitions that hit the cap in adaptive mode */
+  int32_t steps;           /* steps run by the call */
+  int64_t iters_total;     /* total over the call's steps of the largest sweep count */
+  float resid_sweep;       /* largest last-sweep residual max |A_rr dlambda| over partitions (m/s) */
+  float resid_exact;       /* natural-map residual of the final iterate (computed when requested) */
+} ovl_step_stats;
+
+/* Create a world from a scene description.  Every body starts in partition 0
+ * of its scene (one partition per scene) until ovl_set_partitions is called.
+ * On success *out owns all device buffers until ovl_destroy_world.
+ * Errors: INVALID_ARG (bad sizes, non-sphere shapes, anisotropic inertia,
+ * joints across scenes or unsorted), OOM, DEVICE. */
+ovl_status ovl_create_world(const ovl_world_desc* desc, const ovl_params* params, const ovl_device_ctx* ctx,
+                            ovl_world** out);
+
+/* Release every buffer of the world.  NULL is ignored. */
+void ovl_destroy_world(ovl_world* w);
+
+/* Replace the step parameters (takes effect at the next step). */
+ovl_status ovl_set_params(ovl_world* w, const ovl_params* params);
+
+/* Set the base partition of every body (the paper's initial partitioning,
+ * section 5.1 and 5.4).  owner[b] is a global partition id inside its scene's
+ * range; parts_per_scene[s] in [1, 64].  halo_k >= 1 is the overlap depth: a
+ * body is active in every partition that owns a body within halo_k hops of
+ * it in the constraint graph (halo_k = 1 puts exactly the interface bodies in
+ * the overlap set; halo_k = gamma + 1 for the paper's growth depth gamma).
+ * beta in [1, 16] is the geodesic search depth of Alg. 5.  Takes effect at
+ * the next step.  Errors: INVALID_ARG. */
+ovl_status ovl_set_partitions(ovl_world* w, const int32_t* owner, int64_t n_bodies, const int32_t* parts_per_scene,
+                              int32_t n_scenes, int32_t halo_k, int32_t beta);
+
+/* Run n_steps steps.  Asynchronous on the world's stream when stats is NULL
+ * (errors then surface at the next synchronising call); with stats non-NULL
+ * the call synchronises, fills *stats for the last step and, if a per-step
+ * buffer overflowed, grows the buffers and re-runs the steps that did not
+ * commit.  compute_exact_residual != 0 also fills stats->resid_exact.
+ * Errors: CAPACITY, NONFINITE (state kept at the last good step), DEVICE;
+ * NOT_CONVERGED is informational (the state advanced). */
+ovl_status ovl_step(ovl_world* w, int32_t n_steps, ovl_step_stats* stats, int32_t compute_exact_residual);
+
+/* Copy the blended states, [n_bodies][13] float32, into dst (host, or device
+ * when dst_is_device != 0).  Synchronises the stream.  Errors: INVALID_ARG
+ * (n_bodies differs), a pending CAPACITY/NONFINITE error, DEVICE. */
+ovl_status ovl_read_state(ovl_world* w, float* dst, int64_t n_bodies, int32_t dst_is_device);
+
+/* Overwrite the states (checkpoint restore, bulk reset).  src as in
+ * ovl_read_state.  Non-finite values are rejected (INVALID_ARG).  The
+ * warm-start cache is cleared unless keep_cache != 0. */
+ovl_status ovl_write_state(ovl_world* w, const float* src, int64_t n_bodies, int32_t src_is_device,
+                           int32_t keep_cache);
+
+/* Wait for all work queued on the world's stream. */
+ovl_status ovl_synchronize(ovl_world* w);
+
+/* Debug/parity export of the last step's intermediate results.  Writes at
+ * most capacity_bytes into dst (host) and the element count into *count
+ * (a NULL dst only queries the count).  Synchronises.  Fields and layouts:
+ *   CONTACT_KEY   u64 [C]  (a<<32)|(bcode<<1)|sub, sorted; bcode = b for a
+ *                          body b > a, N + plane index, N + P + sphere index
+ *   CONTACT_GEOM  f32 [C*10] n(3), phi, ra(3), rb(3)
+ *   ADJ_OFF       i32 [N+1]; ADJ i32 [adj_off[N]] (per vertex sorted, unique,
+ *                          padded slots hold -1)
+ *   MASK          u64 [N]  local partition bits of every body
+ *   PART_REP_OFF  i32 [G+1]; REP_BODY i32 [R] partition-major, bodies ascending
+ *   REP_D         i32 [R]  geodesic distance (0 = none within beta), partition-major
+ *   REP_W         f32 [R]  blend weight, partition-major
+ *   PART_COPY_OFF i32 [G+1]; COPY_KIND i32 [M] (0 joint, 1 contact); COPY_KEY u64 [M]
+ *   COPY_IA, COPY_IB i32 [M] local replica indices (-1 static); COPY_COLOUR i32 [M]
+ *   COPY_LAMBDA0, COPY_LAMBDA f32 [M*3] warm start and final impulses, uid order
+ *   REP_STATE     f32 [R*13] replica states after integration, partition-major
+ *   PART_ITERS    i32 [G]; PART_RESID f32 [G]
+ *   CACHE         packed warm-start cache of the last step, uid order:
+ *                 CACHE_PART i32 [M], CACHE_KIND i32 [M], CACHE_KEY u64 [M], CACHE_VAL f32 [M*4]
+ *   PART_COL_OFF  i32 [G*65] colour offsets (relative to the partition start)
+ */
+enum {
+  OVL_DBG_CONTACT_KEY = 0,
+  OVL_DBG_CONTACT_GEOM,
+  OVL_DBG_ADJ_OFF,
+  OVL_DBG_ADJ,
+  OVL_DBG_MASK,
+  OVL_DBG_PART_REP_OFF,
+  OVL_DBG_REP_BODY,
+  OVL_DBG_REP_D,
+  OVL_DBG_REP_W,
+  OVL_DBG_PART_COPY_OFF,
+  OVL_DBG_COPY_KIND,
+  OVL_DBG_COPY_KEY,
+  OVL_DBG_COPY_IA,
+  OVL_DBG_COPY_IB,
+  OVL_DBG_COPY_COLOUR,
+  OVL_DBG_COPY_LAMBDA0,
+  OVL_DBG_COPY_LAMBDA,
+  OVL_DBG_REP_STATE,
+  OVL_DBG_PART_ITERS,
+  OVL_DBG_PART_RESID,
+  OVL_DBG_CACHE_PART,
+  OVL_DBG_CACHE_KIND,
+  OVL_DBG_CACHE_KEY,
+  OVL_DBG_CACHE_VAL,
+  OVL_DBG_PART_COL_OFF,
+  OVL_DBG_NFIELDS
+};
+ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int64_t capacity_bytes, int64_t* count);
+
+/* Force the sweep count of every partition of the next step (parity checks
+ * of adaptive runs); iters == NULL clears it.  [G] entries, each >= 0. */
+ovl_status ovl_force_iters(ovl_world* w, const int32_t* iters, int32_t n_parts);
+
+/* Cumulative counters of a world since its creation (synchronises). */
+typedef struct {
+  int64_t steps;              /* committed steps */
+  int64_t sweeps_max_total;   /* sum over steps of the largest sweep count of a partition */
+  int64_t sweeps_part_total;  /* sum over steps and partitions of the sweep counts */
+  int64_t unconverged_total;  /* partitions that hit the cap in adaptive mode */
+  int64_t pgs_bytes;          /* algorithmic bytes of all Gauss-Seidel sweeps: per sweep and constraint
+                                 copy 220 B (two bodies), 164 B (one body and a static), 192 B (joint) */
+  int64_t pgs_launches;       /* solver launches timed with HIP events (profiling on) */
+  double pgs_ms;              /* their summed duration, ms, measured on the world's stream */
+} ovl_counters;
+ovl_status ovl_get_counters(ovl_world* w, ovl_counters* out);
+
+/* Turn HIP-event timing of the solver kernel on (1) or off (0).  Events are
+ * recorded on the world's stream around every Gauss-Seidel launch and summed
+ * by ovl_get_counters. */
+ovl_status ovl_profile(ovl_world* w, int32_t enable);
+
+/* Last error text of the world (never NULL; "" when none).  NULL world:
+ * the last error of a failed ovl_create_world on this thread. */
+const char* ovl_last_error(const ovl_world* w);
+
+/* Library version string. */
+const char* ovl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

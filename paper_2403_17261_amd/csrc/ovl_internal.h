@@ -1,0 +1,187 @@
+// Internal declarations of the ovl library (device buffers and kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ovl {
+
+constexpr int kMaxParts = 64;        // partitions per scene (u64 membership mask)
+constexpr int kMaxColours = 64;      // colours per partition (u64 used-colour mask)
+constexpr int kColStride = kMaxColours + 1;
+constexpr int kPgsBlock = 1024;      // one workgroup per partition
+constexpr int kLdsReps = 4800;       // replicas whose velocities fit in LDS (8 floats each)
+constexpr int kBlock = 256;          // generic per-item kernels
+
+// device scalar slots
+enum Scal {
+  SC_NCONTACT = 0,   // contacts found
+  SC_NADJ,           // adjacency entries
+  SC_NREP,           // replicas
+  SC_NCOPY,          // constraint copies
+  SC_FLAGS,          // error flags (bit set = failure of this step)
+  SC_PREV_NCOPY,     // copies in the warm-start cache
+  SC_COMMITTED,      // steps whose blend committed
+  SC_NJCOPY,         // joint copies
+  SC_NCCOPY,         // contact copies
+  SC_NOVERLAP,       // bodies in >= 2 partitions
+  SC_COUNT = 16
+};
+
+enum Flag {
+  F_CONTACT_CAP = 1,
+  F_ADJ_CAP = 2,
+  F_REP_CAP = 4,
+  F_COPY_CAP = 8,
+  F_COLOUR_CAP = 16,
+  F_NONFINITE = 32,
+};
+
+// Everything a kernel may touch.  Passed by value to every kernel.
+struct WP {
+  // sizes and capacities
+  int32_t N, S, J, P, Q, G, T;   // bodies, scenes, joints, planes, static spheres, partitions, hash buckets
+  int32_t Ccap, Mcap, Rcap, Acap;
+  float cs;                      // grid cell edge
+  // parameters
+  float dt, gx, gy, gz, cfm, erp, tol;
+  int32_t max_iters, adaptive, warmstart, halo_k, beta;
+  uint32_t seed;
+  int32_t forced;                // 1: part_force_iters holds each partition's sweep count
+  // static body data
+  const int32_t* b_scene;
+  const float* b_radius;
+  const float* b_invm;
+  const float* b_invI;
+  // scenes
+  const float* s_mu;
+  const float* s_margin;
+  const int32_t* s_plane_off;
+  const float* planes;          // [P*4]
+  const int32_t* s_ssph_off;
+  const float* ssph;            // [Q*4]
+  const int32_t* s_body_off;    // [S+1]
+  const int32_t* s_joint_off;   // [S+1]
+  const int32_t* s_part_base;   // [S+1]
+  // joints
+  const int32_t* j_ab;          // [J*2]
+  const float* j_anchor;        // [J*6]
+  const int32_t* jadj_off;      // [N+1] joint partners per body, sorted
+  const int32_t* jadj;
+  // partitions
+  const int32_t* owner_local;   // [N] owner - base of the body's scene
+  const int32_t* part_force_iters;  // [G]
+  // canonical state, component-major [13][N]
+  float* st;
+  // grid
+  int32_t* cell;                // [3N]
+  uint32_t* bucket;             // [N]
+  int32_t* bcount;              // [T+1]
+  int32_t* bstart;              // [T+1]
+  int32_t* bfill;               // [T]
+  int32_t* bbody;               // [N]
+  // contacts
+  int32_t* ccount;              // [N+1]
+  int32_t* coff;                // [N+1]
+  uint32_t* c_bkey;             // [Ccap] (bcode<<1)|sub
+  int32_t* c_a;                 // [Ccap]
+  float* c_geom;                // [10][Ccap]: n(3), phi, ra(3), rb(3)
+  // graph
+  int32_t* deg;                 // [N+1]
+  int32_t* adj_off;             // [N+1]
+  int32_t* adj;                 // [Acap]
+  int32_t* adj_fill;            // [N]
+  // masks
+  uint64_t* mask;               // [N]
+  uint64_t* mask_tmp;           // [N]
+  uint64_t* reach;              // [N]
+  uint64_t* reach_tmp;          // [N]
+  // replicas
+  int32_t* rep_cnt;             // [N+1]
+  int32_t* rep_off_bm;          // [N+1]
+  int32_t* rep_D_bm;            // [Rcap]
+  int32_t* rep_pm_of_bm;        // [Rcap]
+  int32_t* rep_body_pm;         // [Rcap]
+  int32_t* part_rep_off;        // [G+1]
+  float* rst;                   // [13][Rcap] replica states after integration
+  float* rep_w_bm;              // [Rcap] blend weight (body-major)
+  // masked compaction scratch: set 0 bodies, 1 joints, 2 contacts
+  int32_t* mc_blk[3];           // [(nblk+1)*64] per-block counts, then exclusive prefixes
+  int32_t* mc_rank0[3];         // [(S+1)*64] rank of each scene start per bit
+  int32_t* mc_psize[3];         // [G+1] items per partition
+  const int32_t* part_scene;    // [G]
+  const int32_t* part_bit;      // [G] local bit of the partition in its scene
+  int32_t* g_tmp;               // [G+1]
+  // copies (uid order)
+  int32_t* part_copy_off;       // [G+1]
+  int32_t* cp_src;              // [Mcap] joint index, or contact index + J
+  int32_t* cp_part;             // [Mcap]
+  int32_t* cp_ia;               // [Mcap]
+  int32_t* cp_ib;               // [Mcap]
+  int32_t* cp_colour;           // [Mcap]
+  int32_t* cp_slot;             // [Mcap]
+  int32_t* inc_off;             // [2*Rcap] replica -> first incident copy, then incident-copy counts
+  int32_t* inc;                 // [2*Mcap]
+  int32_t* part_col_off;        // [G*65]
+  int32_t* part_ncol;           // [G]
+  // rows (slot order = colour-sorted within each partition)
+  int32_t* r_ia;                // [Mcap] local replica index
+  int32_t* r_ib;                // [Mcap] local replica index or -1
+  float* r_f;                   // [RF_COUNT][Mcap]
+  float* r_lam;                 // [3][Mcap]
+  float* r_lam0;                // [3][Mcap]
+  // warm-start cache (uid order of the last committed step)
+  int32_t* wc_part;             // [Mcap]
+  int32_t* wc_kind;             // [Mcap]
+  uint64_t* wc_key;             // [Mcap]
+  float* wc_val;                // [4][Mcap]
+  // per-partition results
+  int32_t* part_iters;          // [G]
+  int32_t* part_nstatic;        // [G] contact copies with a static body
+  float* part_resid;            // [G]
+  float* stat_f;                // [4]: exact residual
+  int64_t* stat_i64;            // [8]: 0 sum over steps of the largest sweep count, 1 unconverged partitions,
+                                //      2 algorithmic bytes of the sweeps, 3 sweeps summed over partitions,
+                                //      4 committed steps
+  // scalars
+  int32_t* scal;                // [SC_COUNT]
+};
+
+// record field indices (component-major in r_f)
+enum RF {
+  RF_D0 = 0,   // row directions d0(3), d1(3), d2(3)
+  RF_RA = 9,   // lever arm of a (3)
+  RF_RB = 12,  // lever arm of b (3)
+  RF_INVD = 15,  // 1/A_rr (3)
+  RF_BIAS = 18,  // bias (3)
+  RF_MU = 21,    // friction coefficient (contact) or -1 (joint)
+  RF_COUNT = 22
+};
+
+inline int nblocks(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// ---- launchers (each returns hipSuccess or the launch error) ----
+// utilities
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+// exclusive scan of n ints: out[0..n] (out[n] = total); optional copy of the total to *total
+hipError_t scan_excl(const int32_t* in, int32_t* out, int64_t n, int32_t* total, int32_t* scratch,
+                     hipStream_t s);
+size_t scan_scratch_ints(int64_t n);
+
+// collision (broad + narrow phase)
+hipError_t launch_collide(const WP& w, int32_t* scan_scratch, hipStream_t s);
+// graph, overlap sets, replicas, geodesic distances, constraint copies
+hipError_t launch_graph(const WP& w, int32_t* scan_scratch, hipStream_t s);
+// colouring, rows, warm start, projected Gauss-Seidel, integration, blending, cache
+hipError_t launch_solve(const WP& w, int32_t* scan_scratch, hipStream_t s, bool exact_residual,
+                        hipEvent_t ev_pgs_begin = nullptr, hipEvent_t ev_pgs_end = nullptr);
+
+// Algorithmic bytes of one Gauss-Seidel sweep per constraint copy: the row
+// record and impulses plus the two bodies' velocity read/write and mass data.
+constexpr int64_t kBytesDynDyn = 220;
+constexpr int64_t kBytesStatic = 164;
+constexpr int64_t kBytesJoint = 192;
+hipError_t pgs_set_attributes();
+
+}  // namespace ovl

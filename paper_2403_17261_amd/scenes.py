@@ -184,13 +184,14 @@ def kmeans_owner(pos: np.ndarray, k: int, iters: int = 10, centroids: Optional[n
         centroids = p[perm[:k]].copy()
     c = centroids.astype(np.float64).copy()
     lab = np.zeros(n, np.int64)
+    p2 = (p * p).sum(1)
     for _ in range(iters):
-        d2 = ((p[:, None, :] - c[None, :, :]) ** 2).sum(-1)
+        d2 = p2[:, None] - 2.0 * (p @ c.T) + (c * c).sum(1)[None, :]
         lab = np.argmin(d2, axis=1)
-        for j in range(c.shape[0]):
-            m = lab == j
-            if m.any():
-                c[j] = p[m].mean(0)
+        cnt = np.bincount(lab, minlength=c.shape[0])
+        for ax in range(3):
+            s_ = np.bincount(lab, weights=p[:, ax], minlength=c.shape[0])
+            c[:, ax] = np.where(cnt > 0, s_ / np.maximum(cnt, 1), c[:, ax])
     return lab.astype(np.int32), c
 
 
@@ -374,7 +375,8 @@ def custom_spheres(pos, radius, mass, vel=None, omega=None, planes=None, ssph=No
         blk["state"][:, 3:7] = np.asarray(quat, np.float32).reshape(-1, 4)
     blk.update(planes=np.zeros((0, 4), np.float32) if planes is None else np.asarray(planes, np.float32),
                ssph=np.zeros((0, 4), np.float32) if ssph is None else np.asarray(ssph, np.float32),
-               mu=mu, margin=np.float32(0.05 * float(np.min(blk["radius"])) if margin is None else margin),
+               mu=mu, margin=np.float32((0.05 * float(np.min(blk["radius"])) if n else 0.025) if margin is None
+                                        else margin),
                owner=np.zeros(n, np.int32) if owner is None else np.asarray(owner, np.int32),
                n_parts=n_parts)
     if joint_ab is not None:

@@ -1,0 +1,96 @@
+"""Helpers for the GPU-vs-oracle parity tests (no method arithmetic here).
+
+compare_step() advances a GPU world by one step from its current state and
+runs the oracle from the very same float32 state and warm-start cache, then
+compares every intermediate result: integer structures bit for bit, floating
+point within the tolerances stated below.
+
+Tolerances (FP32 GPU path against the FP64 oracle after one step):
+  velocity   |v - v_ref| <= 1e-4 * max(|v_ref|, g h)          per body
+  spin       |w - w_ref| <= 1e-4 * max(|w_ref|, g h / r)      per body
+  position   |x - x_ref| <= 1e-6 * (1 + |x_ref|) + h * (velocity bound)
+  weights    |w - w_ref| <= 1e-6
+"""
+import sys
+
+import numpy as np
+
+import oracle
+
+G_ACC = 9.81
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def adjacency_sets(off, adj):
+    return [tuple(sorted(int(u) for u in adj[off[v]:off[v + 1]] if u >= 0)) for v in range(len(off) - 1)]
+
+
+def oracle_kwargs(sc, params, halo_k, beta):
+    return dict(dt=params.dt, gravity=tuple(params.gravity), cfm=params.cfm, erp=params.erp,
+                max_iters=params.max_iters, tol=params.tol, adaptive=params.mode == 1,
+                warmstart=params.warmstart == 1, seed=params.seed, halo_k=halo_k, beta=beta)
+
+
+def check_state(sc, gpu, ref, dt, label=""):
+    r = sc.radius.astype(np.float64)
+    gh = G_ACC * dt
+    v, vr = gpu[:, 7:10].astype(np.float64), ref[:, 7:10]
+    w, wr = gpu[:, 10:13].astype(np.float64), ref[:, 10:13]
+    ev = np.linalg.norm(v - vr, axis=1) / np.maximum(np.linalg.norm(vr, axis=1), gh)
+    ew = np.linalg.norm(w - wr, axis=1) / np.maximum(np.linalg.norm(wr, axis=1), gh / r)
+    vb = 1e-4 * np.maximum(np.linalg.norm(vr, axis=1), gh)
+    ex = np.linalg.norm(gpu[:, 0:3] - ref[:, 0:3], axis=1) - (1e-6 * (1 + np.linalg.norm(ref[:, 0:3], axis=1)) + dt * vb)
+    qd = np.minimum(np.linalg.norm(gpu[:, 3:7] - ref[:, 3:7], axis=1), np.linalg.norm(gpu[:, 3:7] + ref[:, 3:7], axis=1))
+    worst = dict(v=float(ev.max(initial=0)), w=float(ew.max(initial=0)), x=float(ex.max(initial=-1)),
+                 q=float(qd.max(initial=0)))
+    log(f"  {label} worst rel dv={worst['v']:.2e} dw={worst['w']:.2e} x-excess={worst['x']:.2e} dq={worst['q']:.2e}")
+    bad_v = np.where(ev > 1e-4)[0]
+    bad_w = np.where(ew > 1e-4)[0]
+    assert len(bad_v) == 0, f"{label}: {len(bad_v)} bodies exceed the velocity tolerance, e.g. {bad_v[:5]} {ev[bad_v[:5]]}"
+    assert len(bad_w) == 0, f"{label}: {len(bad_w)} bodies exceed the spin tolerance, e.g. {bad_w[:5]} {ew[bad_w[:5]]}"
+    assert worst["x"] <= 0.0, f"{label}: position error {worst['x']}"
+    assert worst["q"] <= 1e-5, f"{label}: quaternion error {worst['q']}"
+
+
+def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, forced=None, label="",
+                 check_lambda0=True):
+    """One GPU step from the world's current state against one oracle step from the same inputs."""
+    halo_k = sc.halo_k if halo_k is None else halo_k
+    beta = sc.beta if beta is None else beta
+    owner = sc.owner if owner is None else owner
+    pps = sc.parts_per_scene if pps is None else pps
+    s0 = w.read_state()
+    cache = w.cache() if params.warmstart else None
+    if forced is not None:
+        w.force_iters(forced)
+    stats = w.step(1, stats=True)
+    g = {k: w.debug(k) for k in ("contact_key", "adj_off", "adj", "mask", "part_rep_off", "rep_body", "rep_d",
+                                 "rep_w", "part_copy_off", "copy_kind", "copy_key", "copy_ia", "copy_ib",
+                                 "copy_colour", "copy_lambda0", "part_iters")}
+    gs = w.read_state()
+    kw = oracle_kwargs(sc, params, halo_k, beta)
+    o = oracle.step(sc, state=s0, owner=owner, parts_per_scene=pps, cache=cache,
+                    forced_iters=forced if forced is not None else None, **kw)
+    log(f"  {label} contacts={len(o['contact_key'])} copies={len(o['copy_key'])} replicas={len(o['rep_body'])} "
+        f"overlap={o['n_overlap']} colours={o['max_colours']} gpu_iters={stats['max_iters']}")
+    assert np.array_equal(g["contact_key"], o["contact_key"]), "contact lists differ"
+    assert adjacency_sets(g["adj_off"], g["adj"]) == adjacency_sets(o["adj_off"], o["adj"]), "graphs differ"
+    assert np.array_equal(g["mask"], o["mask"]), "overlap masks differ"
+    assert np.array_equal(g["part_rep_off"], o["part_rep_off"]), "replica offsets differ"
+    assert np.array_equal(g["rep_body"], o["rep_body"]), "replica tables differ"
+    assert np.array_equal(g["rep_d"], o["rep_d"]), "geodesic distances differ"
+    assert np.abs(g["rep_w"] - o["rep_w"]).max(initial=0) <= 1e-6, "weights differ"
+    for k in ("part_copy_off", "copy_kind", "copy_key", "copy_ia", "copy_ib", "copy_colour"):
+        assert np.array_equal(g[k], o[k]), f"{k} differs"
+    if check_lambda0 and len(o["copy_lambda0"]):
+        d0 = np.abs(g["copy_lambda0"] - o["copy_lambda0"]).max()
+        scale = max(1.0, np.abs(o["copy_lambda0"]).max())
+        assert d0 <= 1e-5 * scale, f"warm start differs by {d0}"
+    if forced is None and not params.mode:
+        assert np.all(g["part_iters"] == params.max_iters)
+    check_state(sc, gs, o["state"], params.dt, label)
+    return stats, o
