@@ -1,13 +1,15 @@
 #!/usr/bin/env python3
-"""Benchmark: body-steps/s of the bowl pile at projected Gauss-Seidel residual <= 1e-4.
+"""Benchmark: body-steps/s at projected Gauss-Seidel residual <= 1e-4 (plain warm start).
 
-Workload: 20,000 spheres (radius U(0.2, 0.5) m, density 1000 kg/m^3) dropped
-into a five-plane bowl, mu = 0.6, h = 1/60 s, 8 k-means spatial partitions with
-a 2-hop overlap (recomputed every 10 steps), geodesic search depth 4, plain
-warm start, adaptive sweeps to a residual of 1e-4 m/s with a cap of 1000.
-The timed region is the scene's full 1000-step run from its initial state
-(the warm-up steps run first and the state is then reset), rebalancing
-included.
+Default workload (--workload tower): the 100,000-sphere tower collapse, a
+50x50x40 lattice of spheres (r = 0.25 m, density 1000 kg/m^3, jitter
+U(+-0.005) m) on a ground plane, mu = 0.5, h = 1/60 s, 64 column partitions
+(8x8) with a 2-hop overlap, geodesic search depth 4, adaptive sweeps to a
+residual of 1e-4 m/s with a cap of 1000, 300 steps from the initial state
+(the warm-up steps run first and the state is then reset).
+
+--workload bowl: the 20,000-sphere bowl pile (8 k-means partitions recomputed
+every 10 steps, 2-hop overlap), 1000 steps.
 
 One GPU only.  Prints one JSON line.  The roofline entry is for the
 Gauss-Seidel kernel: algorithmic bytes of all sweeps of the timed steps (per
@@ -72,20 +74,28 @@ def run_loop(w, sc, steps, state0, owner0, cent0, rebalance_iters=3):
     return owner, cent
 
 
-def cpu_baseline(n_steps, tol, cap):
-    """The oracle (single thread, double precision) on the settled bowl pile written by oracle/pile_state.py."""
+def cpu_baseline(workload, n_steps, tol, cap):
+    """The oracle (single thread, double precision) on a bounded sample of the workload."""
     import oracle
     from paper_2403_17261_amd import scenes
 
-    path = os.path.join(ROOT, "oracle", "data", "bowl20k_seed0_t300.npz")
-    if not os.path.exists(path):
-        return None
-    d = np.load(path)
-    sc = scenes.config2(0)
-    st, owner = d["state"], d["owner"]
     kw = dict(adaptive=True, tol=tol, max_iters=cap)
-    o = oracle.step(sc, state=st, owner=owner, **kw)           # untimed: fills the warm-start cache
-    st = o["state"].astype(np.float32)
+    if workload == "tower":
+        # a 25x25x40 sub-tower in 4x4 columns: partitions of the benchmark's size, from t = 0
+        sc = scenes.config5(0, nx=25, ny=25, nz=40, cols=4)
+        st, owner, o = sc.state, sc.owner, None
+        what = (f"the first {n_steps} steps of a 25x25x40 sub-tower (25,000 spheres, 4x4 column partitions of the "
+                f"benchmark's partition size) from t = 0")
+    else:
+        path = os.path.join(ROOT, "oracle", "data", "bowl20k_seed0_t300.npz")
+        if not os.path.exists(path):
+            return None
+        d = np.load(path)
+        sc = scenes.config2(0)
+        st, owner = d["state"], d["owner"]
+        o = oracle.step(sc, state=st, owner=owner, **kw)           # untimed: fills the warm-start cache
+        st = o["state"].astype(np.float32)
+        what = f"{n_steps} steps of the 20,000-sphere bowl pile from its oracle-computed state at step 300"
     t0 = time.perf_counter()
     sweeps = 0
     for _ in range(n_steps):
@@ -95,21 +105,21 @@ def cpu_baseline(n_steps, tol, cap):
     dt = time.perf_counter() - t0
     return {
         "value": sc.n_bodies * n_steps / dt, "unit": "body-steps/s", "cores": 1, "kind": "oracle",
-        "sample": f"{n_steps} oracle steps (double precision, one thread, adaptive sweeps to 1e-4, cap {cap}) "
-                  f"of the 20,000-sphere bowl pile from its oracle-computed state at step 300 "
-                  f"(mean {sweeps / n_steps:.0f} sweeps per step, {dt:.1f} s)",
+        "sample": f"oracle (double precision, one thread, adaptive sweeps to {tol:g}, cap {cap}): {what}; "
+                  f"mean {sweeps / n_steps:.0f} sweeps per step, {dt:.1f} s",
     }
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--workload", choices=["tower", "bowl"], default="tower")
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", choices=["adaptive", "fixed"], default="adaptive")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cap", type=int, default=1000)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -124,12 +134,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    sc = scenes.config2(0)
+    sc = scenes.config5(0) if args.workload == "tower" else scenes.config2(0)
+    if args.steps is None:
+        args.steps = sc.steps
     mode = ovl.MODE_ADAPTIVE if args.mode == "adaptive" else ovl.MODE_FIXED
     cap = args.cap if mode == ovl.MODE_ADAPTIVE else sc.iters
     p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN)
     w = ovl.World(sc, p)
-    owner0, cent0 = sc.owner.copy(), sc.centroids[0].copy()
+    owner0 = sc.owner.copy()
+    cent0 = sc.centroids[0].copy() if sc.rebalance_every else None
     w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
     log(f"warm-up: {args.warmup} steps")
     run_loop(w, sc, args.warmup, sc.state, owner0, cent0)
@@ -165,7 +178,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle steps")
-        cpu = cpu_baseline(args.cpu_steps, args.tol, args.cap)
+        cpu = cpu_baseline(args.workload, args.cpu_steps, args.tol, args.cap)
     out = {
         "metric": "body-steps/s at PGS residual <=1e-4; learned warm-start vs plain PGS",
         "value": value,
@@ -180,9 +193,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "bowl pile: 20,000 spheres r~U(0.2,0.5) m, density 1000, five-plane bowl, mu 0.6, h 1/60 s, "
-                        "8 k-means partitions (recomputed every 10 steps), 2-hop overlap, beta 4, first "
-                        f"{args.steps} steps from the initial drop",
+            "workload": (f"tower collapse: 50x50x40 spheres r 0.25 m, density 1000, jitter 0.005 m, mu 0.5, "
+                         f"h 1/60 s, 64 column partitions, 2-hop overlap, beta 4, first {args.steps} steps"
+                         if args.workload == "tower" else
+                         f"bowl pile: 20,000 spheres r~U(0.2,0.5) m, density 1000, five-plane bowl, mu 0.6, "
+                         f"h 1/60 s, 8 k-means partitions (recomputed every 10 steps), 2-hop overlap, beta 4, "
+                         f"first {args.steps} steps from the initial drop"),
             "n_bodies": sc.n_bodies, "partitions": int(sc.parts_per_scene[0]), "halo_k": sc.halo_k,
             "beta": sc.beta, "sweeps": f"{args.mode}, tol {args.tol}, cap {cap}", "warm_start": "plain",
             "mean_sweeps_per_step": round(sweeps_mean, 2), "unconverged_partition_steps": int(unconv),

@@ -13,8 +13,8 @@
 // the float state with a fixed operation order and no contraction, so the
 // contact list is identical to any other implementation that follows the
 // same order.  Static planes and static spheres of the scene are tested per
-// body.  Contact records (normal from a to b, gap, lever arms to the midpoint
-// of the two surface points) are computed in double and stored as float.
+// body.  Contact records (normal from a to b, gap, lever-arm lengths to the
+// midpoint of the two surface points) are computed in double, stored as float.
 //
 // Output order: per body a ascending, keys (bcode<<1 | sub) ascending, so the
 // whole list is sorted by (a<<32)|(bcode<<1)|sub without a global sort: a
@@ -141,8 +141,11 @@ __global__ void k_contact_count(WP w) {
   w.ccount[a] = n;
 }
 
-// geometry of one contact, in double, stored as float
-__device__ void contact_geometry(const WP& w, int a, uint32_t bkey, float* g /*10*/) {
+// geometry of one contact in double, stored as float: normal from a towards b,
+// gap, and the lever-arm lengths: both arms point at the midpoint of the two
+// surface points (r_a = l_a n, r_b = -l_b n), so a contact's impulse pair
+// carries no net angular momentum
+__device__ void contact_geometry(const WP& w, int a, uint32_t bkey, float* g /*6*/) {
   const int N = w.N;
   const uint32_t bc = bkey >> 1;
   const double xa = w.st[a], ya = w.st[N + a], za = w.st[2 * N + a], ra = w.b_radius[a];
@@ -189,12 +192,8 @@ __device__ void contact_geometry(const WP& w, int a, uint32_t bkey, float* g /*1
   g[1] = (float)n[1];
   g[2] = (float)n[2];
   g[3] = (float)phi;
-  g[4] = (float)(la * n[0]);
-  g[5] = (float)(la * n[1]);
-  g[6] = (float)(la * n[2]);
-  g[7] = (float)(-lb * n[0]);
-  g[8] = (float)(-lb * n[1]);
-  g[9] = (float)(-lb * n[2]);
+  g[4] = (float)la;
+  g[5] = (float)lb;
 }
 
 __global__ void k_contact_write(WP w) {
@@ -221,11 +220,11 @@ __global__ void k_contact_write(WP w) {
     w.c_bkey[j + 1] = k;
   }
   for (int i = o0; i < o1; ++i) {
-    float g[10];
+    float g[6];
     contact_geometry(w, a, w.c_bkey[i], g);
     w.c_a[i] = a;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) w.c_geom[(int64_t)k * w.Ccap + i] = g[k];
+    for (int k = 0; k < 6; ++k) w.c_geom[(int64_t)k * w.Ccap + i] = g[k];
   }
 }
 

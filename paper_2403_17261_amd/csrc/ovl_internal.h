@@ -10,7 +10,7 @@ constexpr int kMaxParts = 64;        // partitions per scene (u64 membership mas
 constexpr int kMaxColours = 64;      // colours per partition (u64 used-colour mask)
 constexpr int kColStride = kMaxColours + 1;
 constexpr int kPgsBlock = 1024;      // one workgroup per partition
-constexpr int kLdsReps = 4800;       // replicas whose velocities fit in LDS (8 floats each)
+constexpr int kLdsReps = 4800;       // replicas whose velocities fit in LDS (two float4 each)
 constexpr int kBlock = 256;          // generic per-item kernels
 
 // device scalar slots
@@ -85,7 +85,7 @@ struct WP {
   int32_t* coff;                // [N+1]
   uint32_t* c_bkey;             // [Ccap] (bcode<<1)|sub
   int32_t* c_a;                 // [Ccap]
-  float* c_geom;                // [10][Ccap]: n(3), phi, ra(3), rb(3)
+  float* c_geom;                // [6][Ccap]: n(3), phi, l_a, l_b (lever arms l_a n and -l_b n)
   // graph
   int32_t* deg;                 // [N+1]
   int32_t* adj_off;             // [N+1]
@@ -125,11 +125,13 @@ struct WP {
   int32_t* part_col_off;        // [G*65]
   int32_t* part_ncol;           // [G]
   // rows (slot order = colour-sorted within each partition)
-  int32_t* r_ia;                // [Mcap] local replica index
-  int32_t* r_ib;                // [Mcap] local replica index or -1
-  float* r_f;                   // [RF_COUNT][Mcap]
-  float* r_lam;                 // [3][Mcap]
-  float* r_lam0;                // [3][Mcap]
+  //   contact: rec0 = (n, a_duff), rec1 = (l_a, l_b, bias_n, mu), rec2 = (1/A_n, 1/A_t1, 1/A_t2, 0)
+  //   joint:   rec0 = (r_a, bias_x), rec1 = (r_b, bias_y), rec2 = (1/A_x, 1/A_y, 1/A_z, bias_z)
+  float4* r_rec;                // [3][Mcap]
+  int2* r_ids;                  // [Mcap] (local replica a | kJointFlag for joints, local replica b or -1)
+  float4* r_lam;                // [Mcap] impulses (3 used)
+  float4* r_lam0;               // [Mcap] warm-start impulses
+  float4* rep_v4;               // [2*Rcap] velocity storage of partitions too large for LDS
   // warm-start cache (uid order of the last committed step)
   int32_t* wc_part;             // [Mcap]
   int32_t* wc_kind;             // [Mcap]
@@ -147,16 +149,7 @@ struct WP {
   int32_t* scal;                // [SC_COUNT]
 };
 
-// record field indices (component-major in r_f)
-enum RF {
-  RF_D0 = 0,   // row directions d0(3), d1(3), d2(3)
-  RF_RA = 9,   // lever arm of a (3)
-  RF_RB = 12,  // lever arm of b (3)
-  RF_INVD = 15,  // 1/A_rr (3)
-  RF_BIAS = 18,  // bias (3)
-  RF_MU = 21,    // friction coefficient (contact) or -1 (joint)
-  RF_COUNT = 22
-};
+constexpr int32_t kJointFlag = 0x40000000;
 
 inline int nblocks(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 

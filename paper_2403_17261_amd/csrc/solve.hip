@@ -49,13 +49,21 @@ __device__ __forceinline__ bool step_failed(const WP& w) {
   return __hip_atomic_load(&w.scal[SC_FLAGS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Duff et al., "Building an Orthonormal Basis, Revisited" (JCGT 2017)
-__device__ __forceinline__ void tangents(f3 n, f3& t1, f3& t2) {
-  float s = copysignf(1.0f, n.z);
-  float a = -1.0f / (s + n.z);
-  float b = n.x * n.y * a;
+// Duff et al., "Building an Orthonormal Basis, Revisited" (JCGT 2017): the
+// only branch is the sign of n_z.  tangents() returns the basis' coefficient
+// a = -1/(s + n_z), which the rows store so the sweeps rebuild t1, t2 with no
+// division.
+__device__ __forceinline__ void tangents_from(f3 n, float a, f3& t1, f3& t2) {
+  const float s = copysignf(1.0f, n.z);
+  const float b = n.x * n.y * a;
   t1 = mk(1.0f + s * n.x * n.x * a, s * b, -s * n.x);
   t2 = mk(b, s + n.y * n.y * a, -n.y);
+}
+
+__device__ __forceinline__ float tangents(f3 n, f3& t1, f3& t2) {
+  const float a = -1.0f / (copysignf(1.0f, n.z) + n.z);
+  tangents_from(n, a, t1, t2);
+  return a;
 }
 
 __device__ __forceinline__ f3 quat_rotate(float qw, float qx, float qy, float qz, f3 v) {
@@ -247,190 +255,235 @@ __global__ void k_rows(WP w) {
   const int slot = w.cp_slot[u];
   const int src = w.cp_src[u];
   const int p = w.cp_part[u];
-  int a, b;
-  f3 d[3], ra, rb;
-  float bias[3], mu;
-  int kind;
-  uint64_t key;
-  if (src < w.J) {
-    kind = 0;
-    key = (uint64_t)src;
-    a = w.j_ab[2 * src];
-    b = w.j_ab[2 * src + 1];
-    const float* an = w.j_anchor + 6 * src;
-    ra = quat_rotate(w.st[3 * N + a], w.st[4 * N + a], w.st[5 * N + a], w.st[6 * N + a], mk(an[0], an[1], an[2]));
-    rb = quat_rotate(w.st[3 * N + b], w.st[4 * N + b], w.st[5 * N + b], w.st[6 * N + b], mk(an[3], an[4], an[5]));
-    f3 xa = mk(w.st[a], w.st[N + a], w.st[2 * N + a]);
-    f3 xb = mk(w.st[b], w.st[N + b], w.st[2 * N + b]);
-    f3 C = sub(add(xa, ra), add(xb, rb));
-    d[0] = mk(-1, 0, 0);
-    d[1] = mk(0, -1, 0);
-    d[2] = mk(0, 0, -1);
-    const float k = w.erp / w.dt;
-    bias[0] = k * C.x;
-    bias[1] = k * C.y;
-    bias[2] = k * C.z;
-    mu = -1.0f;
-  } else {
-    kind = 1;
-    const int c = src - w.J;
-    a = w.c_a[c];
-    const uint32_t bk = w.c_bkey[c];
-    key = ((uint64_t)a << 32) | bk;
-    b = (bk >> 1) < (uint32_t)N ? (int)(bk >> 1) : -1;
-    const int64_t C = w.Ccap;
-    d[0] = mk(w.c_geom[c], w.c_geom[C + c], w.c_geom[2 * C + c]);
-    const float phi = w.c_geom[3 * C + c];
-    ra = mk(w.c_geom[4 * C + c], w.c_geom[5 * C + c], w.c_geom[6 * C + c]);
-    rb = mk(w.c_geom[7 * C + c], w.c_geom[8 * C + c], w.c_geom[9 * C + c]);
-    tangents(d[0], d[1], d[2]);
-    if (b < 0) atomicAdd(&w.part_nstatic[p], 1);
-    bias[0] = phi > 0.0f ? phi / w.dt : w.erp * phi / w.dt;
-    bias[1] = 0.0f;
-    bias[2] = 0.0f;
-    mu = w.s_mu[w.b_scene[a]];
-  }
-  const float ima = w.b_invm[a], iia = w.b_invI[a];
-  const float imb = b >= 0 ? w.b_invm[b] : 0.0f, iib = b >= 0 ? w.b_invI[b] : 0.0f;
   const int64_t MC = w.Mcap;
-  w.r_ia[slot] = w.cp_ia[u];
-  w.r_ib[slot] = w.cp_ib[u];
-  float* f = w.r_f;
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    f3 aa = cross(ra, d[r]);
-    float A = ima + iia * dot(aa, aa);
-    if (b >= 0) {
-      f3 ab = cross(rb, d[r]);
-      A += imb + iib * dot(ab, ab);
-    }
-    A += w.cfm;
-    f[(RF_D0 + 3 * r) * MC + slot] = d[r].x;
-    f[(RF_D0 + 3 * r + 1) * MC + slot] = d[r].y;
-    f[(RF_D0 + 3 * r + 2) * MC + slot] = d[r].z;
-    f[(RF_INVD + r) * MC + slot] = 1.0f / A;
-    f[(RF_BIAS + r) * MC + slot] = bias[r];
-  }
-  f[(RF_RA + 0) * MC + slot] = ra.x;
-  f[(RF_RA + 1) * MC + slot] = ra.y;
-  f[(RF_RA + 2) * MC + slot] = ra.z;
-  f[(RF_RB + 0) * MC + slot] = rb.x;
-  f[(RF_RB + 1) * MC + slot] = rb.y;
-  f[(RF_RB + 2) * MC + slot] = rb.z;
-  f[RF_MU * MC + slot] = mu;
-  // warm start
   float l0 = 0.0f, l1 = 0.0f, l2 = 0.0f;
   const int prevM = w.scal[SC_PREV_NCOPY];
-  if (w.warmstart && prevM > 0) {
-    int hit = cache_find(w, prevM, p, kind, key);
-    if (hit >= 0) {
-      const float* v = w.wc_val;
-      if (kind == 0) {
-        l0 = v[hit];
-        l1 = v[MC + hit];
-        l2 = v[2 * MC + hit];
-      } else {
-        float ln = fmaxf(v[hit], 0.0f);
-        f3 fw = mk(v[MC + hit], v[2 * MC + hit], v[3 * MC + hit]);
-        float bnd = mu * ln;
+  const bool warm = w.warmstart && prevM > 0;
+  if (src < w.J) {
+    const int a = w.j_ab[2 * src], b = w.j_ab[2 * src + 1];
+    const float* an = w.j_anchor + 6 * src;
+    const f3 ra = quat_rotate(w.st[3 * N + a], w.st[4 * N + a], w.st[5 * N + a], w.st[6 * N + a],
+                              mk(an[0], an[1], an[2]));
+    const f3 rb = quat_rotate(w.st[3 * N + b], w.st[4 * N + b], w.st[5 * N + b], w.st[6 * N + b],
+                              mk(an[3], an[4], an[5]));
+    // C = (x_a + r_a) - (x_b + r_b), grouped so that the difference of the two
+    // nearby centres is taken first (exact in float) instead of cancelling two
+    // rounded sums of large coordinates
+    const f3 dx = mk(w.st[a] - w.st[b], w.st[N + a] - w.st[N + b], w.st[2 * N + a] - w.st[2 * N + b]);
+    const f3 C = add(dx, sub(ra, rb));
+    const float k = w.erp / w.dt;
+    const float ima = w.b_invm[a], iia = w.b_invI[a], imb = w.b_invm[b], iib = w.b_invI[b];
+    // rows along -e_x, -e_y, -e_z: |r x e_k|^2 = |r|^2 - r_k^2
+    const float raa = dot(ra, ra), rbb = dot(rb, rb);
+    const float Ax = ima + imb + iia * (raa - ra.x * ra.x) + iib * (rbb - rb.x * rb.x) + w.cfm;
+    const float Ay = ima + imb + iia * (raa - ra.y * ra.y) + iib * (rbb - rb.y * rb.y) + w.cfm;
+    const float Az = ima + imb + iia * (raa - ra.z * ra.z) + iib * (rbb - rb.z * rb.z) + w.cfm;
+    w.r_rec[slot] = make_float4(ra.x, ra.y, ra.z, k * C.x);
+    w.r_rec[MC + slot] = make_float4(rb.x, rb.y, rb.z, k * C.y);
+    w.r_rec[2 * MC + slot] = make_float4(1.0f / Ax, 1.0f / Ay, 1.0f / Az, k * C.z);
+    w.r_ids[slot] = make_int2(w.cp_ia[u] | kJointFlag, w.cp_ib[u]);
+    if (warm) {
+      const int hit = cache_find(w, prevM, p, 0, (uint64_t)src);
+      if (hit >= 0) {
+        l0 = w.wc_val[hit];
+        l1 = w.wc_val[MC + hit];
+        l2 = w.wc_val[2 * MC + hit];
+      }
+    }
+  } else {
+    const int c = src - w.J;
+    const int a = w.c_a[c];
+    const uint32_t bk = w.c_bkey[c];
+    const int b = (bk >> 1) < (uint32_t)N ? (int)(bk >> 1) : -1;
+    const int64_t CC = w.Ccap;
+    const f3 n = mk(w.c_geom[c], w.c_geom[CC + c], w.c_geom[2 * CC + c]);
+    const float phi = w.c_geom[3 * CC + c];
+    const float la = w.c_geom[4 * CC + c], lb = w.c_geom[5 * CC + c];
+    f3 t1, t2;
+    const float ad = tangents(n, t1, t2);
+    if (b < 0) atomicAdd(&w.part_nstatic[p], 1);
+    const float bias = phi > 0.0f ? phi / w.dt : w.erp * phi / w.dt;
+    const float mu = w.s_mu[w.b_scene[a]];
+    const float ima = w.b_invm[a], iia = w.b_invI[a];
+    const float imb = b >= 0 ? w.b_invm[b] : 0.0f, iib = b >= 0 ? w.b_invI[b] : 0.0f;
+    // sphere contact: r_a = l_a n, r_b = -l_b n, so r x n = 0 and |r x t|^2 = l^2
+    const float An = ima + imb + w.cfm;
+    const float At = ima + imb + iia * la * la + iib * lb * lb + w.cfm;
+    w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
+    w.r_rec[MC + slot] = make_float4(la, lb, bias, mu);
+    w.r_rec[2 * MC + slot] = make_float4(1.0f / An, 1.0f / At, 1.0f / At, 0.0f);
+    w.r_ids[slot] = make_int2(w.cp_ia[u], b >= 0 ? w.cp_ib[u] : -1);
+    if (warm) {
+      const int hit = cache_find(w, prevM, p, 1, ((uint64_t)a << 32) | bk);
+      if (hit >= 0) {
+        const float* v = w.wc_val;
+        const float ln = fmaxf(v[hit], 0.0f);
+        const f3 fw = mk(v[MC + hit], v[2 * MC + hit], v[3 * MC + hit]);
+        const float bnd = mu * ln;
         l0 = ln;
-        l1 = fminf(fmaxf(dot(fw, d[1]), -bnd), bnd);
-        l2 = fminf(fmaxf(dot(fw, d[2]), -bnd), bnd);
+        l1 = fminf(fmaxf(dot(fw, t1), -bnd), bnd);
+        l2 = fminf(fmaxf(dot(fw, t2), -bnd), bnd);
       }
     }
   }
-  w.r_lam0[slot] = l0;
-  w.r_lam0[MC + slot] = l1;
-  w.r_lam0[2 * MC + slot] = l2;
-  w.r_lam[slot] = l0;
-  w.r_lam[MC + slot] = l1;
-  w.r_lam[2 * MC + slot] = l2;
+  w.r_lam0[slot] = make_float4(l0, l1, l2, 0.0f);
+  w.r_lam[slot] = make_float4(l0, l1, l2, 0.0f);
 }
 
 // ---------------------------------------------------------- Gauss-Seidel ----
+// Replica velocity storage: two float4 per replica, (v, 1/m) and (w, 1/I), in
+// LDS, or for partitions too large for LDS in the partition's slice of rep_v4.
 
-// replica velocity storage: LDS (component-major [8][nr]) or, for partitions
-// too large for LDS, the partition's own slice of the replica-state array
-template <bool kLds>
-struct Vel;
-
-template <>
-struct Vel<true> {
-  float* s;
-  int n;
-  __device__ __forceinline__ float* ptr(int comp, int r) const { return s + comp * n + r; }
-};
-
-template <>
-struct Vel<false> {
-  float* s;  // rst + r0 ; component stride Rcap
-  int64_t stride;
-  __device__ __forceinline__ float* ptr(int comp, int r) const { return s + comp * stride + r; }
-};
-// components: 0..2 v, 3..5 w, 6 invm, 7 invI
-
-struct Row3 {
-  f3 d[3];
-  f3 ra, rb;
-  float invd[3], bias[3], mu;
+struct Rec {
+  float4 r0, r1, r2, lam;
   int ia, ib;
+  bool joint;
 };
 
-__device__ __forceinline__ void load_row(const WP& w, int slot, Row3& R) {
+__device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R) {
   const int64_t MC = w.Mcap;
-  const float* f = w.r_f;
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    R.d[r] = mk(f[(RF_D0 + 3 * r) * MC + slot], f[(RF_D0 + 3 * r + 1) * MC + slot], f[(RF_D0 + 3 * r + 2) * MC + slot]);
-    R.invd[r] = f[(RF_INVD + r) * MC + slot];
-    R.bias[r] = f[(RF_BIAS + r) * MC + slot];
-  }
-  R.ra = mk(f[RF_RA * MC + slot], f[(RF_RA + 1) * MC + slot], f[(RF_RA + 2) * MC + slot]);
-  R.rb = mk(f[RF_RB * MC + slot], f[(RF_RB + 1) * MC + slot], f[(RF_RB + 2) * MC + slot]);
-  R.mu = f[RF_MU * MC + slot];
-  R.ia = w.r_ia[slot];
-  R.ib = w.r_ib[slot];
+  R.r0 = w.r_rec[slot];
+  R.r1 = w.r_rec[MC + slot];
+  R.r2 = w.r_rec[2 * MC + slot];
+  const int2 id = w.r_ids[slot];
+  R.joint = (id.x & kJointFlag) != 0;
+  R.ia = id.x & ~kJointFlag;
+  R.ib = id.y;
+  R.lam = w.r_lam[slot];
 }
 
-struct Body6 {
+struct Bod {
   f3 v, w;
   float im, ii;
 };
 
-template <class V>
-__device__ __forceinline__ Body6 load_body(const V& V_, int r) {
-  Body6 b;
-  b.v = mk(*V_.ptr(0, r), *V_.ptr(1, r), *V_.ptr(2, r));
-  b.w = mk(*V_.ptr(3, r), *V_.ptr(4, r), *V_.ptr(5, r));
-  b.im = *V_.ptr(6, r);
-  b.ii = *V_.ptr(7, r);
-  return b;
+__device__ __forceinline__ Bod ld_body(const float4* V, int r) {
+  const float4 a = V[2 * r], b = V[2 * r + 1];
+  return {mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), a.w, b.w};
 }
 
-template <class V>
-__device__ __forceinline__ void store_vel(const V& V_, int r, const Body6& b) {
-  *V_.ptr(0, r) = b.v.x;
-  *V_.ptr(1, r) = b.v.y;
-  *V_.ptr(2, r) = b.v.z;
-  *V_.ptr(3, r) = b.w.x;
-  *V_.ptr(4, r) = b.w.y;
-  *V_.ptr(5, r) = b.w.z;
+__device__ __forceinline__ void st_body(float4* V, int r, const Bod& B) {
+  V[2 * r] = make_float4(B.v.x, B.v.y, B.v.z, B.im);
+  V[2 * r + 1] = make_float4(B.w.x, B.w.y, B.w.z, B.ii);
 }
 
-// apply impulse dl of row r
-__device__ __forceinline__ void apply(Body6& A, Body6& B, bool hasB, const Row3& R, int r, f3 angA, f3 angB,
-                                      float dl) {
-  A.v = sub(A.v, scale(R.d[r], A.im * dl));
-  A.w = sub(A.w, scale(angA, A.ii * dl));
-  if (hasB) {
-    B.v = add(B.v, scale(R.d[r], B.im * dl));
-    B.w = add(B.w, scale(angB, B.ii * dl));
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Contact (three rows n, t1, t2).  With r_a = l_a n and r_b = -l_b n:
+//   J_n v  = n.(v_b - v_a)
+//   J_t1 v = t1.(v_b - v_a) - t2.(l_a w_a + l_b w_b)
+//   J_t2 v = t2.(v_b - v_a) + t1.(l_a w_a + l_b w_b)
+// and the impulse dl of a row moves v_a by -dl/m_a d, v_b by +dl/m_b d, and the
+// spins by the matching lever-arm terms.  `solve` false applies lam as given
+// (warm start) instead of projecting.
+template <bool solve>
+__device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl) {
+  const f3 n = mk(R.r0.x, R.r0.y, R.r0.z);
+  f3 t1, t2;
+  tangents_from(n, R.r0.w, t1, t2);
+  const float la = R.r1.x, lb = R.r1.y, bias = R.r1.z, mu = R.r1.w;
+  float dl;
+  // normal
+  if (solve) {
+    const f3 dv = sub(B.v, A.v);
+    const float wv = dot(n, dv) + bias + cfm * lam.x;
+    const float nl = fmaxf(lam.x - wv * R.r2.x, 0.0f);
+    dl = nl - lam.x;
+    lam.x = nl;
+    rl = fmaxf(rl, fabsf(dl) * rcp_fast(R.r2.x));
+  } else {
+    dl = lam.x;
   }
+  A.v = sub(A.v, scale(n, A.im * dl));
+  B.v = add(B.v, scale(n, B.im * dl));
+  const float hi = mu * lam.x;
+  // tangent 1
+  if (solve) {
+    const f3 dv = sub(B.v, A.v);
+    const f3 sw = add(scale(A.w, la), scale(B.w, lb));
+    const float wv = dot(t1, dv) - dot(t2, sw) + cfm * lam.y;
+    const float nl = fminf(fmaxf(lam.y - wv * R.r2.y, -hi), hi);
+    dl = nl - lam.y;
+    lam.y = nl;
+    rl = fmaxf(rl, fabsf(dl) * rcp_fast(R.r2.y));
+  } else {
+    dl = lam.y;
+  }
+  A.v = sub(A.v, scale(t1, A.im * dl));
+  B.v = add(B.v, scale(t1, B.im * dl));
+  A.w = sub(A.w, scale(t2, A.ii * la * dl));
+  B.w = sub(B.w, scale(t2, B.ii * lb * dl));
+  // tangent 2
+  if (solve) {
+    const f3 dv = sub(B.v, A.v);
+    const f3 sw = add(scale(A.w, la), scale(B.w, lb));
+    const float wv = dot(t2, dv) + dot(t1, sw) + cfm * lam.z;
+    const float nl = fminf(fmaxf(lam.z - wv * R.r2.z, -hi), hi);
+    dl = nl - lam.z;
+    lam.z = nl;
+    rl = fmaxf(rl, fabsf(dl) * rcp_fast(R.r2.z));
+  } else {
+    dl = lam.z;
+  }
+  A.v = sub(A.v, scale(t2, A.im * dl));
+  B.v = add(B.v, scale(t2, B.im * dl));
+  A.w = add(A.w, scale(t1, A.ii * la * dl));
+  B.w = add(B.w, scale(t1, B.ii * lb * dl));
+}
+
+// Ball joint, rows along -e_k: J_k v = (v_a + w_a x r_a - v_b - w_b x r_b)_k;
+// the impulse dl of row k moves v_a by +dl/m_a e_k and w_a by +dl I_a^-1 (r_a x e_k),
+// and body b the opposite way.
+template <bool solve>
+__device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl) {
+  const f3 ra = mk(R.r0.x, R.r0.y, R.r0.z), rb = mk(R.r1.x, R.r1.y, R.r1.z);
+  const float bias[3] = {R.r0.w, R.r1.w, R.r2.w};
+  const float invd[3] = {R.r2.x, R.r2.y, R.r2.z};
+  float* l = &lam.x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float dl;
+    if (solve) {
+      const f3 pa = add(A.v, cross(A.w, ra));
+      const f3 pb = add(B.v, cross(B.w, rb));
+      const float vr = k == 0 ? pa.x - pb.x : (k == 1 ? pa.y - pb.y : pa.z - pb.z);
+      const float wv = vr + bias[k] + cfm * l[k];
+      const float nl = l[k] - wv * invd[k];
+      dl = nl - l[k];
+      l[k] = nl;
+      rl = fmaxf(rl, fabsf(dl) * rcp_fast(invd[k]));
+    } else {
+      dl = l[k];
+    }
+    const f3 e = mk(k == 0 ? 1.0f : 0.0f, k == 1 ? 1.0f : 0.0f, k == 2 ? 1.0f : 0.0f);
+    A.v = add(A.v, scale(e, A.im * dl));
+    B.v = sub(B.v, scale(e, B.im * dl));
+    A.w = add(A.w, scale(cross(ra, e), A.ii * dl));
+    B.w = sub(B.w, scale(cross(rb, e), B.ii * dl));
+  }
+}
+
+template <bool solve>
+__device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& rl, int slot) {
+  Bod A = ld_body(V, R.ia);
+  Bod B;
+  const bool hasB = R.ib >= 0;
+  if (hasB)
+    B = ld_body(V, R.ib);
+  else
+    B = {mk(0, 0, 0), mk(0, 0, 0), 0.0f, 0.0f};
+  if (R.joint)
+    joint_rows<solve>(R, A, B, w.cfm, R.lam, rl);
+  else
+    contact_rows<solve>(R, A, B, w.cfm, R.lam, rl);
+  st_body(V, R.ia, A);
+  if (hasB) st_body(V, R.ib, B);
+  if (solve) w.r_lam[slot] = R.lam;
 }
 
 template <bool kLds>
 __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
-  extern __shared__ float sm[];
+  extern __shared__ float4 sm4[];
   __shared__ int coff[kColStride];
   __shared__ float red[kPgsBlock / 64];
   __shared__ int failed_s;
@@ -453,95 +506,50 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   const int s0 = w.part_copy_off[p];
   const int ncol = w.part_ncol[p];
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
-  Vel<kLds> V;
-  if constexpr (kLds) {
-    V.s = sm;
-    V.n = nr;
-  } else {
-    V.s = w.rst + r0;
-    V.stride = w.Rcap;
-  }
-  // load replica velocities (gravity applied: v~ = v + h g) and inverse masses
+  float4* V = kLds ? sm4 : w.rep_v4 + 2 * (int64_t)r0;
+  // replica velocities with gravity applied (v~ = v + h g) and inverse masses
   const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
   for (int r = tid; r < nr; r += kPgsBlock) {
     const int b = w.rep_body_pm[r0 + r];
-    *V.ptr(0, r) = w.st[7 * N + b] + hgx;
-    *V.ptr(1, r) = w.st[8 * N + b] + hgy;
-    *V.ptr(2, r) = w.st[9 * N + b] + hgz;
-    *V.ptr(3, r) = w.st[10 * N + b];
-    *V.ptr(4, r) = w.st[11 * N + b];
-    *V.ptr(5, r) = w.st[12 * N + b];
-    *V.ptr(6, r) = w.b_invm[b];
-    *V.ptr(7, r) = w.b_invI[b];
+    V[2 * r] = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
+    V[2 * r + 1] = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
   }
   __syncthreads();
-  const int64_t MC = w.Mcap;
+  float rl = 0.0f;
   // warm-start impulses enter in solve order
   for (int c = 0; c < ncol; ++c) {
     const int e = s0 + coff[c + 1];
     for (int slot = s0 + coff[c] + tid; slot < e; slot += kPgsBlock) {
-      float l[3] = {w.r_lam[slot], w.r_lam[MC + slot], w.r_lam[2 * MC + slot]};
-      if (l[0] == 0.0f && l[1] == 0.0f && l[2] == 0.0f) continue;
-      Row3 R;
-      load_row(w, slot, R);
-      const bool hasB = R.ib >= 0;
-      Body6 A = load_body(V, R.ia);
-      Body6 B;
-      if (hasB) B = load_body(V, R.ib);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) apply(A, B, hasB, R, r, cross(R.ra, R.d[r]), cross(R.rb, R.d[r]), l[r]);
-      store_vel(V, R.ia, A);
-      if (hasB) store_vel(V, R.ib, B);
+      Rec R;
+      load_rec(w, slot, R);
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false>(w, V, R, rl, slot);
     }
     __syncthreads();
   }
-  // sweeps
+  // sweeps; the first slot of the next colour is loaded while the current colour is solved
   const int cap = w.forced ? w.part_force_iters[p] : w.max_iters;
   int it = 0;
   float rho = 0.0f;
+  Rec cur;
+  bool has_cur = ncol > 0 && coff[0] + tid < coff[1];
+  if (has_cur) load_rec(w, s0 + coff[0] + tid, cur);
   while (it < cap) {
-    float rl = 0.0f;
+    rl = 0.0f;
     for (int c = 0; c < ncol; ++c) {
+      const int cn = c + 1 < ncol ? c + 1 : 0;
+      Rec nxt;
+      const bool has_nxt = coff[cn] + tid < coff[cn + 1];
+      if (has_nxt) load_rec(w, s0 + coff[cn] + tid, nxt);
+      if (has_cur) do_slot<true>(w, V, cur, rl, s0 + coff[c] + tid);
       const int e = s0 + coff[c + 1];
-      for (int slot = s0 + coff[c] + tid; slot < e; slot += kPgsBlock) {
-        Row3 R;
-        load_row(w, slot, R);
-        float l[3] = {w.r_lam[slot], w.r_lam[MC + slot], w.r_lam[2 * MC + slot]};
-        const bool hasB = R.ib >= 0;
-        Body6 A = load_body(V, R.ia);
-        Body6 B;
-        if (hasB) B = load_body(V, R.ib);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const f3 angA = cross(R.ra, R.d[r]);
-          const f3 angB = cross(R.rb, R.d[r]);
-          float vr = -dot(R.d[r], A.v) - dot(angA, A.w);
-          if (hasB) vr += dot(R.d[r], B.v) + dot(angB, B.w);
-          const float wv = vr + R.bias[r] + w.cfm * l[r];
-          float lo, hi;
-          if (R.mu < 0.0f) {
-            lo = -INFINITY;
-            hi = INFINITY;
-          } else if (r == 0) {
-            lo = 0.0f;
-            hi = INFINITY;
-          } else {
-            hi = R.mu * l[0];
-            lo = -hi;
-          }
-          const float nl = fminf(fmaxf(l[r] - wv * R.invd[r], lo), hi);
-          const float dl = nl - l[r];
-          l[r] = nl;
-          apply(A, B, hasB, R, r, angA, angB, dl);
-          rl = fmaxf(rl, fabsf(dl) / R.invd[r]);
-        }
-        store_vel(V, R.ia, A);
-        if (hasB) store_vel(V, R.ib, B);
-        w.r_lam[slot] = l[0];
-        w.r_lam[MC + slot] = l[1];
-        w.r_lam[2 * MC + slot] = l[2];
+      for (int slot = s0 + coff[c] + tid + kPgsBlock; slot < e; slot += kPgsBlock) {
+        Rec R;
+        load_rec(w, slot, R);
+        do_slot<true>(w, V, R, rl, slot);
       }
       __syncthreads();
+      cur = nxt;
+      has_cur = has_nxt;
     }
     rho = block_max<kPgsBlock>(rl, red);
     ++it;
@@ -552,10 +560,10 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   bool bad = false;
   for (int r = tid; r < nr; r += kPgsBlock) {
     const int b = w.rep_body_pm[r0 + r];
-    Body6 B = load_body(V, r);
-    float x = w.st[b] + h * B.v.x;
-    float y = w.st[N + b] + h * B.v.y;
-    float z = w.st[2 * N + b] + h * B.v.z;
+    const Bod B = ld_body(V, r);
+    const float x = w.st[b] + h * B.v.x;
+    const float y = w.st[N + b] + h * B.v.y;
+    const float z = w.st[2 * N + b] + h * B.v.z;
     float qw = w.st[3 * N + b], qx = w.st[4 * N + b], qy = w.st[5 * N + b], qz = w.st[6 * N + b];
     const float wx = B.w.x, wy = B.w.y, wz = B.w.z;
     const float dw = -(wx * qx + wy * qy + wz * qz);
@@ -567,7 +575,7 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
     qy += 0.5f * h * dy;
     qz += 0.5f * h * dz;
     const float nn = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-    float out[13] = {x, y, z, qw * nn, qx * nn, qy * nn, qz * nn, B.v.x, B.v.y, B.v.z, B.w.x, B.w.y, B.w.z};
+    const float out[13] = {x, y, z, qw * nn, qx * nn, qy * nn, qz * nn, B.v.x, B.v.y, B.v.z, B.w.x, B.w.y, B.w.z};
 #pragma unroll
     for (int k = 0; k < 13; ++k) {
       bad |= !isfinite(out[k]);
@@ -645,24 +653,24 @@ __global__ void k_cache(WP w) {
   const int64_t MC = w.Mcap;
   const int slot = w.cp_slot[u];
   const int src = w.cp_src[u];
-  const float l0 = w.r_lam[slot], l1 = w.r_lam[MC + slot], l2 = w.r_lam[2 * MC + slot];
+  const float4 l = w.r_lam[slot];
   w.wc_part[u] = w.cp_part[u];
   if (src < w.J) {
     w.wc_kind[u] = 0;
     w.wc_key[u] = (uint64_t)src;
-    w.wc_val[u] = l0;
-    w.wc_val[MC + u] = l1;
-    w.wc_val[2 * MC + u] = l2;
+    w.wc_val[u] = l.x;
+    w.wc_val[MC + u] = l.y;
+    w.wc_val[2 * MC + u] = l.z;
     w.wc_val[3 * MC + u] = 0.0f;
   } else {
     const int c = src - w.J;
     w.wc_kind[u] = 1;
     w.wc_key[u] = ((uint64_t)w.c_a[c] << 32) | w.c_bkey[c];
-    const float* f = w.r_f;
-    f3 t1 = mk(f[(RF_D0 + 3) * MC + slot], f[(RF_D0 + 4) * MC + slot], f[(RF_D0 + 5) * MC + slot]);
-    f3 t2 = mk(f[(RF_D0 + 6) * MC + slot], f[(RF_D0 + 7) * MC + slot], f[(RF_D0 + 8) * MC + slot]);
-    f3 fw = add(scale(t1, l1), scale(t2, l2));
-    w.wc_val[u] = l0;
+    const float4 r0 = w.r_rec[slot];
+    f3 t1, t2;
+    tangents_from(mk(r0.x, r0.y, r0.z), r0.w, t1, t2);
+    const f3 fw = add(scale(t1, l.y), scale(t2, l.z));
+    w.wc_val[u] = l.x;
     w.wc_val[MC + u] = fw.x;
     w.wc_val[2 * MC + u] = fw.y;
     w.wc_val[3 * MC + u] = fw.z;
@@ -691,7 +699,9 @@ __global__ void k_commit(WP w) {
   w.stat_i64[4] += 1;
 }
 
-// natural-map residual of the final iterate, one workgroup per partition
+// natural-map residual of the final iterate, one workgroup per partition: for
+// every row, A_rr |lambda - clamp(lambda - w/A_rr, lo, hi)| with w the row's
+// constraint velocity at the final velocities
 __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
   __shared__ float red[4];
   __shared__ int failed_s;
@@ -701,36 +711,60 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
   if (failed_s) return;
   const int r0 = w.part_rep_off[p];
   const int s0 = w.part_copy_off[p], s1 = w.part_copy_off[p + 1];
-  const int64_t MC = w.Mcap, RC = w.Rcap;
+  const int64_t RC = w.Rcap;
   float e = 0.0f;
   for (int slot = s0 + threadIdx.x; slot < s1; slot += 256) {
-    Row3 R;
-    load_row(w, slot, R);
-    float l[3] = {w.r_lam[slot], w.r_lam[MC + slot], w.r_lam[2 * MC + slot]};
+    Rec R;
+    load_rec(w, slot, R);
+    Bod A, B;
     const int ra_ = r0 + R.ia;
-    f3 va = mk(w.rst[7 * RC + ra_], w.rst[8 * RC + ra_], w.rst[9 * RC + ra_]);
-    f3 wa = mk(w.rst[10 * RC + ra_], w.rst[11 * RC + ra_], w.rst[12 * RC + ra_]);
-    f3 vb = mk(0, 0, 0), wb = mk(0, 0, 0);
+    A.v = mk(w.rst[7 * RC + ra_], w.rst[8 * RC + ra_], w.rst[9 * RC + ra_]);
+    A.w = mk(w.rst[10 * RC + ra_], w.rst[11 * RC + ra_], w.rst[12 * RC + ra_]);
+    B.v = mk(0, 0, 0);
+    B.w = mk(0, 0, 0);
     if (R.ib >= 0) {
       const int rb_ = r0 + R.ib;
-      vb = mk(w.rst[7 * RC + rb_], w.rst[8 * RC + rb_], w.rst[9 * RC + rb_]);
-      wb = mk(w.rst[10 * RC + rb_], w.rst[11 * RC + rb_], w.rst[12 * RC + rb_]);
+      B.v = mk(w.rst[7 * RC + rb_], w.rst[8 * RC + rb_], w.rst[9 * RC + rb_]);
+      B.w = mk(w.rst[10 * RC + rb_], w.rst[11 * RC + rb_], w.rst[12 * RC + rb_]);
     }
-    for (int r = 0; r < 3; ++r) {
-      f3 angA = cross(R.ra, R.d[r]), angB = cross(R.rb, R.d[r]);
-      float vr = -dot(R.d[r], va) - dot(angA, wa) + dot(R.d[r], vb) + dot(angB, wb);
-      float wv = vr + R.bias[r] + w.cfm * l[r];
-      float lo = -INFINITY, hi = INFINITY;
-      if (R.mu >= 0.0f) {
-        if (r == 0)
-          lo = 0.0f;
-        else {
-          hi = R.mu * l[0];
-          lo = -hi;
-        }
+    float vr[3], invd[3], bias[3], lo[3], hi[3];
+    const float* l = &R.lam.x;
+    if (R.joint) {
+      const f3 ra = mk(R.r0.x, R.r0.y, R.r0.z), rb = mk(R.r1.x, R.r1.y, R.r1.z);
+      const f3 d = sub(add(A.v, cross(A.w, ra)), add(B.v, cross(B.w, rb)));
+      vr[0] = d.x;
+      vr[1] = d.y;
+      vr[2] = d.z;
+      bias[0] = R.r0.w;
+      bias[1] = R.r1.w;
+      bias[2] = R.r2.w;
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = -INFINITY;
+        hi[k] = INFINITY;
       }
-      float pr = fminf(fmaxf(l[r] - wv * R.invd[r], lo), hi);
-      e = fmaxf(e, fabsf(l[r] - pr) / R.invd[r]);
+    } else {
+      const f3 n = mk(R.r0.x, R.r0.y, R.r0.z);
+      f3 t1, t2;
+      tangents_from(n, R.r0.w, t1, t2);
+      const f3 dv = sub(B.v, A.v);
+      const f3 sw = add(scale(A.w, R.r1.x), scale(B.w, R.r1.y));
+      vr[0] = dot(n, dv);
+      vr[1] = dot(t1, dv) - dot(t2, sw);
+      vr[2] = dot(t2, dv) + dot(t1, sw);
+      bias[0] = R.r1.z;
+      bias[1] = bias[2] = 0.0f;
+      lo[0] = 0.0f;
+      hi[0] = INFINITY;
+      hi[1] = hi[2] = R.r1.w * l[0];
+      lo[1] = lo[2] = -hi[1];
+    }
+    invd[0] = R.r2.x;
+    invd[1] = R.r2.y;
+    invd[2] = R.r2.z;
+    for (int k = 0; k < 3; ++k) {
+      const float wv = vr[k] + bias[k] + w.cfm * l[k];
+      const float pr = fminf(fmaxf(l[k] - wv * invd[k], lo[k]), hi[k]);
+      e = fmaxf(e, fabsf(l[k] - pr) / invd[k]);
     }
   }
   e = block_max<256>(e, red);
@@ -741,7 +775,7 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
 
 hipError_t pgs_set_attributes() {
   hipError_t e = hipFuncSetAttribute((const void*)k_pgs<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     8 * kLdsReps * (int)sizeof(float));
+                                     2 * kLdsReps * (int)sizeof(float4));
   return e;
 }
 
@@ -759,7 +793,7 @@ hipError_t launch_solve(const WP& w, int32_t* sc, hipStream_t s, bool exact_resi
   }
   if (w.G > 0) {
     if (ev_pgs_begin && (e = hipEventRecord(ev_pgs_begin, s))) return e;
-    k_pgs<true><<<w.G, kPgsBlock, 8 * kLdsReps * sizeof(float), s>>>(w);
+    k_pgs<true><<<w.G, kPgsBlock, 2 * kLdsReps * sizeof(float4), s>>>(w);
     if ((e = hipGetLastError())) return e;
     k_pgs<false><<<w.G, kPgsBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;

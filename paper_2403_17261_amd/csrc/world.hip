@@ -124,7 +124,7 @@ struct ovl_world {
     w.Acap = Acap;
     w.c_bkey = alloc<uint32_t>(g, Ccap, ok);
     w.c_a = alloc<int32_t>(g, Ccap, ok);
-    w.c_geom = alloc<float>(g, (size_t)10 * Ccap, ok);
+    w.c_geom = alloc<float>(g, (size_t)6 * Ccap, ok);
     w.adj = alloc<int32_t>(g, Acap, ok);
     w.rep_D_bm = alloc<int32_t>(g, Rcap, ok);
     w.rep_pm_of_bm = alloc<int32_t>(g, Rcap, ok);
@@ -139,11 +139,11 @@ struct ovl_world {
     w.cp_ib = alloc<int32_t>(g, Mcap, ok);
     w.cp_colour = alloc<int32_t>(g, Mcap, ok);
     w.cp_slot = alloc<int32_t>(g, Mcap, ok);
-    w.r_ia = alloc<int32_t>(g, Mcap, ok);
-    w.r_ib = alloc<int32_t>(g, Mcap, ok);
-    w.r_f = alloc<float>(g, (size_t)RF_COUNT * Mcap, ok);
-    w.r_lam = alloc<float>(g, (size_t)3 * Mcap, ok);
-    w.r_lam0 = alloc<float>(g, (size_t)3 * Mcap, ok);
+    w.r_rec = alloc<float4>(g, (size_t)3 * Mcap, ok);
+    w.r_ids = alloc<int2>(g, Mcap, ok);
+    w.r_lam = alloc<float4>(g, Mcap, ok);
+    w.r_lam0 = alloc<float4>(g, Mcap, ok);
+    w.rep_v4 = alloc<float4>(g, (size_t)2 * Rcap, ok);
     w.wc_part = alloc<int32_t>(g, Mcap, ok);
     w.wc_kind = alloc<int32_t>(g, Mcap, ok);
     w.wc_key = alloc<uint64_t>(g, Mcap, ok);
@@ -755,10 +755,19 @@ extern "C" ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int
     }
     case OVL_DBG_CONTACT_GEOM: {
       std::vector<float> gcol;
-      ok = dl(w, gcol, p.c_geom, (size_t)10 * p.Ccap);
+      ok = dl(w, gcol, p.c_geom, (size_t)6 * p.Ccap);
       std::vector<float> g((size_t)10 * C);
-      for (int i = 0; i < C && ok; ++i)
-        for (int k = 0; k < 10; ++k) g[10 * (size_t)i + k] = gcol[(size_t)k * p.Ccap + i];
+      for (int i = 0; i < C && ok; ++i) {
+        const float n[3] = {gcol[i], gcol[(size_t)p.Ccap + i], gcol[2 * (size_t)p.Ccap + i]};
+        const float la = gcol[4 * (size_t)p.Ccap + i], lb = gcol[5 * (size_t)p.Ccap + i];
+        float* o = &g[10 * (size_t)i];
+        for (int k = 0; k < 3; ++k) {
+          o[k] = n[k];
+          o[4 + k] = la * n[k];
+          o[7 + k] = -lb * n[k];
+        }
+        o[3] = gcol[3 * (size_t)p.Ccap + i];
+      }
       put(g.data(), (size_t)10 * C, 4);
       break;
     }
@@ -842,12 +851,17 @@ extern "C" ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int
     case OVL_DBG_COPY_LAMBDA0:
     case OVL_DBG_COPY_LAMBDA: {
       std::vector<int32_t> slot;
-      std::vector<float> lc;
-      ok = dl(w, slot, p.cp_slot, M) && dl(w, lc, field == OVL_DBG_COPY_LAMBDA ? p.r_lam : p.r_lam0, (size_t)3 * p.Mcap);
+      std::vector<float4> lc;
+      ok = dl(w, slot, p.cp_slot, M) && dl(w, lc, field == OVL_DBG_COPY_LAMBDA ? (const float4*)p.r_lam
+                                                                             : (const float4*)p.r_lam0, (size_t)p.Mcap);
       std::vector<float> o((size_t)3 * M);
       for (int u = 0; u < M && ok; ++u)
-        if (slot[u] >= 0 && slot[u] < p.Mcap)
-          for (int k = 0; k < 3; ++k) o[3 * (size_t)u + k] = lc[(size_t)k * p.Mcap + slot[u]];
+        if (slot[u] >= 0 && slot[u] < p.Mcap) {
+          const float4 l = lc[slot[u]];
+          o[3 * (size_t)u] = l.x;
+          o[3 * (size_t)u + 1] = l.y;
+          o[3 * (size_t)u + 2] = l.z;
+        }
       put(o.data(), (size_t)3 * M, 4);
       break;
     }
