@@ -74,7 +74,11 @@ typedef struct {
 } ovl_world_desc;
 
 enum { OVL_MODE_FIXED = 0, OVL_MODE_ADAPTIVE = 1 };
-enum { OVL_WARM_NONE = 0, OVL_WARM_PLAIN = 1 };
+enum { OVL_WARM_NONE = 0, OVL_WARM_PLAIN = 1, OVL_WARM_LEARNED = 2 };
+
+/* Parameters of the warm-start network 12 -> 64 -> 64 -> 3 (ReLU), flat:
+ * W1[12][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3], input index first. */
+#define OVL_MLP_PARAMS 5187
 
 /* Step parameters.  Eq. 2's compliance C is cfm * identity; its
  * stabilisation term is applied as erp * phi / h for penetrations and phi / h
@@ -186,6 +190,7 @@ ovl_status ovl_synchronize(ovl_world* w);
  *   CACHE         packed warm-start cache of the last step, uid order:
  *                 CACHE_PART i32 [M], CACHE_KIND i32 [M], CACHE_KEY u64 [M], CACHE_VAL f32 [M*4]
  *   PART_COL_OFF  i32 [G*65] colour offsets (relative to the partition start)
+ *   COPY_FEAT, COPY_LAMBDAL, PART_GUARD, PART_RHO0: see below
  */
 enum {
   OVL_DBG_CONTACT_KEY = 0,
@@ -213,9 +218,58 @@ enum {
   OVL_DBG_CACHE_KEY,
   OVL_DBG_CACHE_VAL,
   OVL_DBG_PART_COL_OFF,
+  OVL_DBG_COPY_FEAT,      /* f32 [M*13] features and impulse scale (feature export or learned mode) */
+  OVL_DBG_COPY_LAMBDAL,   /* f32 [M*3] learned start, uid order (learned mode) */
+  OVL_DBG_PART_GUARD,     /* i32 [G] 1 when the learned start was kept */
+  OVL_DBG_PART_RHO0,      /* f32 [G*2] initial residual of the plain and the learned start */
   OVL_DBG_NFIELDS
 };
 ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int64_t capacity_bytes, int64_t* count);
+
+/* Warm-start mode of the following steps (not in the paper; a solver
+ * accelerator).  OVL_WARM_PLAIN: the previous step's impulses of the same
+ * (partition, kind, key).  OVL_WARM_LEARNED: for contacts, the network's
+ * prediction from twelve per-contact features (BF16 matrix-core inference),
+ * projected on the contact's bounds; per partition it is kept only when its
+ * initial natural-map residual is below the plain start's, else the plain
+ * start is used (the guard).  params: OVL_MLP_PARAMS floats (learned mode
+ * only; copied).  ovl_params.warmstart is overridden.  Errors: INVALID_ARG. */
+ovl_status ovl_set_warmstart(ovl_world* w, int32_t mode, const float* params, int64_t n_params);
+
+/* Write the per-contact features during the following steps (1) or not (0);
+ * needed by ovl_collect_training_rows. */
+ovl_status ovl_set_feature_export(ovl_world* w, int32_t enable);
+
+/* Training rows of the last step's contact copies (uid order): features
+ * [n][12] and targets [n][3] = final impulses (n, t1, t2) / s, with s the
+ * copy's impulse scale.  Host buffers of capacity_rows rows; *n_rows gets the
+ * count (NULL buffers only query it).  Errors: INVALID_ARG (no features
+ * exported, buffers too small). */
+ovl_status ovl_collect_training_rows(ovl_world* w, float* features, float* targets, int64_t capacity_rows,
+                                     int64_t* n_rows);
+
+/* Force the learned/plain choice of every partition of the next steps
+ * (parity checks of the guard); choice[g] in {-1 decide, 0 plain, 1 learned};
+ * NULL clears it. */
+ovl_status ovl_force_guard(ovl_world* w, const int32_t* choice, int32_t n_parts);
+
+/* Trainer of the warm-start network on the device (FP32, Adam with
+ * beta1 0.9, beta2 0.999, eps 1e-8; deterministic).  Rows are features
+ * [n][12] and targets [n][3]; the loss is their mean squared error. */
+typedef struct ovl_mlp ovl_mlp;
+ovl_status ovl_mlp_create(const float* params, int64_t n_params, const ovl_device_ctx* ctx, ovl_mlp** out);
+void ovl_mlp_destroy(ovl_mlp* m);
+/* One Adam step on a batch; x, t on the host, or on the device when on_device != 0. */
+ovl_status ovl_mlp_train_step(ovl_mlp* m, const float* x, const float* t, int64_t n, float lr, int32_t on_device,
+                              float* loss);
+/* Gradient (OVL_MLP_PARAMS floats, host) and loss of a batch without an update. */
+ovl_status ovl_mlp_gradient(ovl_mlp* m, const float* x, const float* t, int64_t n, int32_t on_device, float* grad,
+                            float* loss);
+ovl_status ovl_mlp_get_params(ovl_mlp* m, float* out, int64_t n_params);
+const char* ovl_mlp_last_error(const ovl_mlp* m);
+/* BF16 matrix-core inference of the network on host rows x [n][12] -> y [n][3]
+ * (the kernel the learned warm start uses). */
+ovl_status ovl_mlp_infer(const float* params, int64_t n_params, const float* x, int64_t n, float* y);
 
 /* Force the sweep count of every partition of the next step (parity checks
  * of adaptive runs); iters == NULL clears it.  [G] entries, each >= 0. */

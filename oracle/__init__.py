@@ -20,7 +20,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 (CONTACT_KEY, CONTACT_N, CONTACT_PHI, CONTACT_RA, CONTACT_RB, ADJ_OFF, ADJ, MASK, PART_REP_OFF, REP_BODY,
  REP_D, REP_W, PART_COPY_OFF, COPY_KIND, COPY_KEY, COPY_IA, COPY_IB, COPY_COLOUR, COPY_DIR, COPY_RA,
  COPY_RB, COPY_ARR, COPY_BIAS, COPY_MU, COPY_LAMBDA0, COPY_LAMBDA, REP_VT, REP_INVM, REP_INVI, REP_STATE,
- STATE, PART_ITERS, PART_RESID, CACHE_PART, CACHE_KIND, CACHE_KEY, CACHE_VAL, STATS) = range(38)
+ STATE, PART_ITERS, PART_RESID, CACHE_PART, CACHE_KIND, CACHE_KEY, CACHE_VAL, STATS, COPY_FEAT, COPY_LAMBDAL,
+ PART_GUARD, PART_RHO0, COPY_DEG) = range(43)
+
+MLP_PARAMS = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 
 _FIELDS = {
     "contact_key": (CONTACT_KEY, np.uint64, 1), "contact_n": (CONTACT_N, np.float64, 3),
@@ -41,6 +44,9 @@ _FIELDS = {
     "cache_part": (CACHE_PART, np.int32, 1), "cache_kind": (CACHE_KIND, np.int32, 1),
     "cache_key": (CACHE_KEY, np.uint64, 1), "cache_val": (CACHE_VAL, np.float32, 4),
     "stats": (STATS, np.float64, 1),
+    "copy_feat": (COPY_FEAT, np.float64, 13), "copy_lambdal": (COPY_LAMBDAL, np.float64, 3),
+    "part_guard": (PART_GUARD, np.int32, 1), "part_rho0": (PART_RHO0, np.float64, 2),
+    "copy_deg": (COPY_DEG, np.int32, 1),
 }
 
 
@@ -56,7 +62,8 @@ class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
                 ("cfm", C.c_double), ("erp", C.c_double), ("tol", C.c_double), ("max_iters", C.c_int32),
                 ("adaptive", C.c_int32), ("warmstart", C.c_int32), ("halo_k", C.c_int32), ("beta", C.c_int32),
-                ("brute_force_contacts", C.c_int32), ("seed", C.c_uint32)]
+                ("brute_force_contacts", C.c_int32), ("seed", C.c_uint32), ("learned", C.c_int32),
+                ("mlp", C.c_void_p), ("forced_guard", C.c_void_p)]
 
 
 class _Cache(C.Structure):
@@ -97,6 +104,9 @@ def lib():
         L.orc_fmix32.argtypes = [C.c_uint32]
         L.orc_tangents.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_blend.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_bf16.restype = C.c_float
+        L.orc_bf16.argtypes = [C.c_float]
+        L.orc_mlp_infer.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -126,8 +136,24 @@ def blend(states, weights):
     return out
 
 
+def bf16(x: float) -> float:
+    return float(lib().orc_bf16(C.c_float(float(x))))
+
+
+def mlp_infer(params, x12):
+    """The warm-start network as the matrix engine evaluates it (bfloat16 operands, exact products)."""
+    P = np.ascontiguousarray(params, np.float32)
+    assert P.size == MLP_PARAMS
+    X = np.ascontiguousarray(x12, np.float64).reshape(-1, 12)
+    Y = np.zeros((X.shape[0], 3))
+    for i in range(X.shape[0]):
+        lib().orc_mlp_infer(P.ctypes.data, X[i].ctypes.data, Y[i].ctypes.data)
+    return Y
+
+
 DEFAULTS = dict(dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), cfm=0.0, erp=0.2, max_iters=20, tol=1e-4,
-                adaptive=False, warmstart=True, halo_k=1, beta=4, seed=0, brute_force=False)
+                adaptive=False, warmstart=True, halo_k=1, beta=4, seed=0, brute_force=False, mlp=None,
+                forced_guard=None)
 
 
 def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced_iters=None, **kw):
@@ -165,6 +191,11 @@ def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced
     pr.max_iters, pr.adaptive, pr.warmstart = int(p["max_iters"]), int(bool(p["adaptive"])), int(bool(p["warmstart"]))
     pr.halo_k, pr.beta, pr.brute_force_contacts = int(p["halo_k"]), int(p["beta"]), int(bool(p["brute_force"]))
     pr.seed = int(p["seed"]) & 0xFFFFFFFF
+    if p["mlp"] is not None:
+        pr.learned = 1
+        pr.mlp = _ptr(arr(p["mlp"], np.float32))
+    if p["forced_guard"] is not None:
+        pr.forced_guard = _ptr(arr(p["forced_guard"], np.int32))
     cp = None
     if cache is not None and len(cache["cache_part"]):
         cc = _Cache()

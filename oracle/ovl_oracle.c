@@ -422,7 +422,9 @@ typedef struct {
   int64_t uid;
   double dir[9], ra[3], rb[3], arr[3], invd[3], bias[3], mu;
   double anga[9], angb[9], ka[9], kb[9];
-  double lam[3], lam0[3];
+  double lam[3], lam0[3], laml[3];
+  double feat[13];
+  int32_t deg;
 } copy_t;
 
 typedef struct {
@@ -544,6 +546,90 @@ void orc_blend(int32_t n, const double* states, const double* w, double* out) {
   double nn = sqrt(acc[3] * acc[3] + acc[4] * acc[4] + acc[5] * acc[5] + acc[6] * acc[6]);
   for (int k = 0; k < 4; ++k) acc[3 + k] /= nn;
   for (int k = 0; k < 13; ++k) out[k] = acc[k];
+}
+
+/* Copy a start (plain, or learned for contacts) into lambda and apply it to
+ * the velocities in solve order. */
+static void apply_start(replica* rp, copy_t* cp, const order_t* od, int64_t nm, int learned) {
+  for (int64_t t = 0; t < nm; ++t) {
+    copy_t* c = &cp[od[t].idx];
+    replica* A = &rp[c->ia];
+    replica* B = c->ib >= 0 ? &rp[c->ib] : NULL;
+    const double* l0 = learned ? c->laml : c->lam0;
+    for (int r = 0; r < 3; ++r) {
+      c->lam[r] = l0[r];
+      if (l0[r] != 0.0) apply_row(A, B, c, r, l0[r]);
+    }
+  }
+}
+
+/* Natural-map residual of a start (max over the partition's rows); the
+ * velocities are restored to v~ afterwards. */
+static double start_residual(replica* rp, int64_t nr, copy_t* cp, const order_t* od, int64_t nm, int learned,
+                             double cfm) {
+  apply_start(rp, cp, od, nm, learned);
+  double e = 0.0;
+  for (int64_t t = 0; t < nm; ++t) {
+    copy_t* c = &cp[od[t].idx];
+    replica* A = &rp[c->ia];
+    replica* B = c->ib >= 0 ? &rp[c->ib] : NULL;
+    for (int r = 0; r < 3; ++r) {
+      double w = row_velocity(A, B, c, r) + c->bias[r] + cfm * c->lam[r];
+      double lo, hi;
+      row_bounds(c, r, &lo, &hi);
+      double x = c->arr[r] * fabs(c->lam[r] - clampd(c->lam[r] - w * c->invd[r], lo, hi));
+      if (x > e) e = x;
+    }
+  }
+  for (int64_t r = 0; r < nr; ++r)
+    for (int k = 0; k < 3; ++k) {
+      rp[r].v[k] = rp[r].vt[k];
+      rp[r].w[k] = rp[r].vt[3 + k];
+    }
+  return e;
+}
+
+/* bfloat16 rounding of a float (round to nearest, ties to even), returned as float */
+float orc_bf16(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  u &= 0xffff0000u;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
+/* The warm-start network 12 -> 64 -> 64 -> 3 with ReLU, evaluated the way a
+ * bfloat16 matrix engine does: inputs, weights and hidden activations rounded
+ * to bfloat16, products accumulated exactly (here in double), biases in
+ * float. */
+void orc_mlp_infer(const float* P, const double* x12, double* y3) {
+  const float* W1 = P;
+  const float* b1 = W1 + ORC_MLP_IN * ORC_MLP_HID;
+  const float* W2 = b1 + ORC_MLP_HID;
+  const float* b2 = W2 + ORC_MLP_HID * ORC_MLP_HID;
+  const float* W3 = b2 + ORC_MLP_HID;
+  const float* b3 = W3 + ORC_MLP_HID * ORC_MLP_OUT;
+  double x[ORC_MLP_IN], h1[ORC_MLP_HID], h2[ORC_MLP_HID];
+  for (int k = 0; k < ORC_MLP_IN; ++k) x[k] = orc_bf16((float)x12[k]);
+  for (int j = 0; j < ORC_MLP_HID; ++j) {
+    double acc = 0.0;
+    for (int k = 0; k < ORC_MLP_IN; ++k) acc += x[k] * orc_bf16(W1[k * ORC_MLP_HID + j]);
+    double v = acc + b1[j];
+    h1[j] = orc_bf16((float)(v > 0.0 ? v : 0.0));
+  }
+  for (int j = 0; j < ORC_MLP_HID; ++j) {
+    double acc = 0.0;
+    for (int k = 0; k < ORC_MLP_HID; ++k) acc += h1[k] * orc_bf16(W2[k * ORC_MLP_HID + j]);
+    double v = acc + b2[j];
+    h2[j] = orc_bf16((float)(v > 0.0 ? v : 0.0));
+  }
+  for (int o = 0; o < ORC_MLP_OUT; ++o) {
+    double acc = 0.0;
+    for (int k = 0; k < ORC_MLP_HID; ++k) acc += h2[k] * orc_bf16(W3[k * ORC_MLP_OUT + o]);
+    y3[o] = acc + b3[o];
+  }
 }
 
 /* local index of body v among the replicas of partition p (bodies ascending) */
@@ -903,6 +989,9 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
     }
     prio_t* pr = (prio_t*)xalloc((size_t)nm * sizeof(prio_t));
     for (int64_t m = m0; m < m1; ++m) {
+      /* conflict degree: other copies of the partition sharing a body */
+      cp[m].deg = ioff[cp[m].ia + 1] - ioff[cp[m].ia] - 1;
+      if (cp[m].ib >= 0) cp[m].deg += ioff[cp[m].ib + 1] - ioff[cp[m].ib] - 1;
       cp[m].colour = -1;
       pr[m - m0].h = orc_fmix32((uint32_t)cp[m].uid ^ prm->seed);
       pr[m - m0].uid = cp[m].uid;
@@ -958,7 +1047,59 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
     }
   }
 
+  /* ---- learned warm start (not in the paper; an accelerator that leaves the
+   * solve unchanged): per contact copy twelve features of the problem at the
+   * start of the step, normalised by the velocity scale g h and the impulse
+   * scale s = g h / (1/m_a + 1/m_b); the network predicts lambda / s, which is
+   * projected on the contact's bounds.  Joints keep the plain start. ---- */
+  {
+    double g = sqrt(prm->gx * prm->gx + prm->gy * prm->gy + prm->gz * prm->gz);
+    double vs = g * h > 0.0 ? g * h : 1.0;
+    for (int64_t m = 0; m < M; ++m) {
+      copy_t* c = &cp[m];
+      for (int k = 0; k < 13; ++k) c->feat[k] = 0.0;
+      for (int r = 0; r < 3; ++r) c->laml[r] = c->lam0[r];
+      if (c->kind != 1) continue;
+      const replica* A = &rep[prep[c->part] + c->ia];
+      const replica* B = c->ib >= 0 ? &rep[prep[c->part] + c->ib] : NULL;
+      const contact* k = &cl.c[c->id];
+      double pa[3], pb[3] = {0, 0, 0}, t[3];
+      cross3(A->vt + 3, c->ra, t);
+      for (int i = 0; i < 3; ++i) pa[i] = A->vt[i] + t[i];
+      double ima = A->invm, imb = 0.0;
+      if (B) {
+        cross3(B->vt + 3, c->rb, t);
+        for (int i = 0; i < 3; ++i) pb[i] = B->vt[i] + t[i];
+        imb = B->invm;
+      }
+      double vr[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
+      double s_imp = vs / (ima + imb);
+      double margin = sc->margin[sc->scene[A->body]];
+      for (int i = 0; i < 3; ++i) c->feat[i] = c->dir[i];
+      c->feat[3] = dot3(vr, c->dir) / vs;
+      c->feat[4] = dot3(vr, c->dir + 3) / vs;
+      c->feat[5] = dot3(vr, c->dir + 6) / vs;
+      c->feat[6] = margin > 0.0 ? k->phi / margin : k->phi;
+      c->feat[7] = ima / (ima + imb);
+      c->feat[8] = imb / (ima + imb);
+      c->feat[9] = c->lam0[0] / s_imp;
+      c->feat[10] = sqrt(c->lam0[1] * c->lam0[1] + c->lam0[2] * c->lam0[2]) / s_imp;
+      c->feat[11] = c->deg / 16.0;
+      c->feat[12] = s_imp;
+      if (prm->learned && prm->mlp) {
+        double y[3];
+        orc_mlp_infer(prm->mlp, c->feat, y);
+        double ln = y[0] * s_imp > 0.0 ? y[0] * s_imp : 0.0;
+        c->laml[0] = ln;
+        c->laml[1] = clampd(y[1] * s_imp, -c->mu * ln, c->mu * ln);
+        c->laml[2] = clampd(y[2] * s_imp, -c->mu * ln, c->mu * ln);
+      }
+    }
+  }
+
   /* ---- projected Gauss-Seidel per partition, colours ascending then uid ---- */
+  int32_t* pguard = (int32_t*)xalloc((size_t)(G ? G : 1) * 4);
+  double* prho0 = (double*)xalloc((size_t)(G ? G : 1) * 16);
   int32_t* piters = (int32_t*)xalloc((size_t)(G ? G : 1) * 4);
   double* presid = (double*)xalloc((size_t)(G ? G : 1) * 8);
   int unconverged = 0;
@@ -972,16 +1113,20 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
       od[m - m0].idx = m;
     }
     qsort(od, (size_t)nm, sizeof(order_t), cmp_order);
-    /* warm-start impulses enter the velocities in solve order */
-    for (int64_t t = 0; t < nm; ++t) {
-      copy_t* c = &cp[od[t].idx];
-      replica* A = &rp[c->ia];
-      replica* B = c->ib >= 0 ? &rp[c->ib] : NULL;
-      for (int r = 0; r < 3; ++r) {
-        c->lam[r] = c->lam0[r];
-        if (c->lam0[r] != 0.0) apply_row(A, B, c, r, c->lam0[r]);
-      }
+    /* with the learned start, keep it only when its initial residual is
+     * below the plain start's (the guard) */
+    int use_learned = 0;
+    if (prm->learned) {
+      double rho_p = start_residual(rp, prep[p + 1] - prep[p], cp, od, nm, 0, prm->cfm);
+      double rho_l = start_residual(rp, prep[p + 1] - prep[p], cp, od, nm, 1, prm->cfm);
+      prho0[2 * p] = rho_p;
+      prho0[2 * p + 1] = rho_l;
+      use_learned = rho_l < rho_p;
+      if (prm->forced_guard && prm->forced_guard[p] >= 0) use_learned = prm->forced_guard[p];
     }
+    pguard[p] = use_learned;
+    /* warm-start impulses enter the velocities in solve order */
+    apply_start(rp, cp, od, nm, use_learned);
     int it = 0;
     double rho = 0.0;
     int cap = forced_iters ? forced_iters[p] : prm->max_iters;
@@ -1013,6 +1158,8 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
   }
   put(res, ORC_PART_ITERS, piters, G);
   put(res, ORC_PART_RESID, presid, G);
+  put(res, ORC_PART_GUARD, pguard, G);
+  put(res, ORC_PART_RHO0, prho0, 2 * G);
 
   /* ---- exact natural-map residual of the final iterate ---- */
   double rho_exact = 0.0, rho_sum = 0.0;
@@ -1091,6 +1238,17 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
     put(res, ORC_COPY_MU, mu, M);
     put(res, ORC_COPY_LAMBDA0, l0, 3 * M);
     put(res, ORC_COPY_LAMBDA, l, 3 * M);
+    double* feat = (double*)xalloc((size_t)M * 13 * 8);
+    double* laml = (double*)xalloc((size_t)M * 24);
+    int32_t* deg = (int32_t*)xalloc((size_t)M * 4);
+    for (int64_t m = 0; m < M; ++m) {
+      for (int k = 0; k < 13; ++k) feat[13 * m + k] = cp[m].feat[k];
+      for (int k = 0; k < 3; ++k) laml[3 * m + k] = cp[m].laml[k];
+      deg[m] = cp[m].deg;
+    }
+    put(res, ORC_COPY_FEAT, feat, 13 * M);
+    put(res, ORC_COPY_LAMBDAL, laml, 3 * M);
+    put(res, ORC_COPY_DEG, deg, M);
     put(res, ORC_CACHE_PART, cpart, M);
     put(res, ORC_CACHE_KIND, ckind, M);
     put(res, ORC_CACHE_KEY, ckey, M);

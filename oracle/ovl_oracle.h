@@ -41,7 +41,15 @@ typedef struct {
   double dt, gx, gy, gz, cfm, erp, tol;
   int32_t max_iters, adaptive, warmstart, halo_k, beta, brute_force_contacts;
   uint32_t seed;
+  int32_t learned;              /* 1: learned warm start for contacts, guarded per partition */
+  const float* mlp;             /* [ORC_MLP_PARAMS] W1[12][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3] */
+  const int32_t* forced_guard;  /* [G] or NULL: 1 learned, 0 plain, -1 decide */
 } orc_params;
+
+#define ORC_MLP_IN 12
+#define ORC_MLP_HID 64
+#define ORC_MLP_OUT 3
+#define ORC_MLP_PARAMS (12 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3)
 
 typedef struct {
   int64_t n;
@@ -93,6 +101,11 @@ enum orc_field {
   ORC_CACHE_VAL,         /* f32 [M*4] */
   ORC_STATS,             /* f64 [8]: exact residual, sum residual, joint violation, n_overlap,
                                       max colours, max iters, error code, unconverged partitions */
+  ORC_COPY_FEAT,         /* f64 [M*13] contact features (12) and impulse scale s (joints: zeros) */
+  ORC_COPY_LAMBDAL,      /* f64 [M*3] learned warm start (contacts; joints: plain) */
+  ORC_PART_GUARD,        /* i32 [G] 1 when the learned start was kept */
+  ORC_PART_RHO0,         /* f64 [G*2] initial residual of the plain and of the learned start */
+  ORC_COPY_DEG,          /* i32 [M] conflict degree */
   ORC_NFIELDS
 };
 
@@ -108,6 +121,8 @@ const char* orc_error(const orc_result* r);
 uint32_t orc_fmix32(uint32_t h);
 void orc_tangents(const double n[3], double t1[3], double t2[3]);
 void orc_blend(int32_t n, const double* states, const double* w, double* out);
+float orc_bf16(float x);
+void orc_mlp_infer(const float* params, const double* x12, double* y3);
 
 #ifdef __cplusplus
 }

@@ -22,16 +22,18 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ovl.h")
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_NONFINITE, ERR_DEVICE, NOT_CONVERGED = range(7)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "NONFINITE", 5: "DEVICE", 6: "NOT_CONVERGED"}
 MODE_FIXED, MODE_ADAPTIVE = 0, 1
-WARM_NONE, WARM_PLAIN = 0, 1
+WARM_NONE, WARM_PLAIN, WARM_LEARNED = 0, 1, 2
+MLP_PARAMS = 5187
 
 DBG_FIELDS = ["contact_key", "contact_geom", "adj_off", "adj", "mask", "part_rep_off", "rep_body", "rep_d", "rep_w",
               "part_copy_off", "copy_kind", "copy_key", "copy_ia", "copy_ib", "copy_colour", "copy_lambda0",
               "copy_lambda", "rep_state", "part_iters", "part_resid", "cache_part", "cache_kind", "cache_key",
-              "cache_val", "part_col_off"]
+              "cache_val", "part_col_off", "copy_feat", "copy_lambdal", "part_guard", "part_rho0"]
 _DBG_DTYPE = {"contact_key": (np.uint64, 1), "contact_geom": (np.float32, 10), "mask": (np.uint64, 1),
               "rep_w": (np.float32, 1), "copy_key": (np.uint64, 1), "copy_lambda0": (np.float32, 3),
               "copy_lambda": (np.float32, 3), "rep_state": (np.float32, 13), "part_resid": (np.float32, 1),
-              "cache_key": (np.uint64, 1), "cache_val": (np.float32, 4)}
+              "cache_key": (np.uint64, 1), "cache_val": (np.float32, 4), "copy_feat": (np.float32, 13),
+              "copy_lambdal": (np.float32, 3), "part_rho0": (np.float32, 2)}
 
 
 class OvlError(RuntimeError):
@@ -85,6 +87,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        # PyTorch bundles its own HIP runtime under the same soname as ROCm's;
+        # loading torch first makes the library bind to that one runtime, so
+        # the process never holds two HIP runtimes.
+        import torch  # noqa: F401
+
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         sig = {
@@ -102,6 +109,17 @@ def lib():
             "ovl_last_error": (C.c_char_p, [P]),
             "ovl_get_counters": (C.c_int, [P, C.POINTER(ovl_counters)]),
             "ovl_profile": (C.c_int, [P, C.c_int32]),
+            "ovl_set_warmstart": (C.c_int, [P, C.c_int32, P, C.c_int64]),
+            "ovl_set_feature_export": (C.c_int, [P, C.c_int32]),
+            "ovl_collect_training_rows": (C.c_int, [P, P, P, C.c_int64, C.POINTER(C.c_int64)]),
+            "ovl_force_guard": (C.c_int, [P, P, C.c_int32]),
+            "ovl_mlp_create": (C.c_int, [P, C.c_int64, C.POINTER(ovl_device_ctx), C.POINTER(P)]),
+            "ovl_mlp_destroy": (None, [P]),
+            "ovl_mlp_train_step": (C.c_int, [P, P, P, C.c_int64, C.c_float, C.c_int32, C.POINTER(C.c_float)]),
+            "ovl_mlp_gradient": (C.c_int, [P, P, P, C.c_int64, C.c_int32, P, C.POINTER(C.c_float)]),
+            "ovl_mlp_get_params": (C.c_int, [P, P, C.c_int64]),
+            "ovl_mlp_last_error": (C.c_char_p, [P]),
+            "ovl_mlp_infer": (C.c_int, [P, C.c_int64, P, C.c_int64, P]),
             "ovl_version": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -292,5 +310,94 @@ class World:
         self._check(lib().ovl_get_counters(self.h, C.byref(c)))
         return {f: getattr(c, f) for f, _ in ovl_counters._fields_}
 
+    def set_warmstart(self, mode, params=None):
+        if params is None:
+            self._check(lib().ovl_set_warmstart(self.h, int(mode), None, 0))
+        else:
+            p = np.ascontiguousarray(params, np.float32)
+            self._check(lib().ovl_set_warmstart(self.h, int(mode), _p(p), p.size))
+
+    def set_feature_export(self, enable=True):
+        self._check(lib().ovl_set_feature_export(self.h, int(bool(enable))))
+
+    def training_rows(self):
+        n = C.c_int64()
+        self._check(lib().ovl_collect_training_rows(self.h, None, None, 0, C.byref(n)))
+        X = np.zeros((n.value, 12), np.float32)
+        T = np.zeros((n.value, 3), np.float32)
+        self._check(lib().ovl_collect_training_rows(self.h, _p(X), _p(T), n.value, C.byref(n)))
+        return X, T
+
+    def force_guard(self, choice):
+        if choice is None:
+            self._check(lib().ovl_force_guard(self.h, None, 0))
+            return
+        c = np.ascontiguousarray(choice, np.int32)
+        self._check(lib().ovl_force_guard(self.h, _p(c), len(c)))
+
     def cache(self):
         return {k: self.debug(k) for k in ("cache_part", "cache_kind", "cache_key", "cache_val")}
+
+
+def ovl_mlp_infer(params, x):
+    """BF16 matrix-core inference of the warm-start network: x [n,12] -> y [n,3]."""
+    p = np.ascontiguousarray(params, np.float32)
+    X = np.ascontiguousarray(x, np.float32).reshape(-1, 12)
+    Y = np.zeros((X.shape[0], 3), np.float32)
+    st = lib().ovl_mlp_infer(_p(p), p.size, _p(X), X.shape[0], _p(Y))
+    if st != OK:
+        raise OvlError(st, "ovl_mlp_infer")
+    return Y
+
+
+class Trainer:
+    """The device trainer of the warm-start network (``ovl_mlp_*``)."""
+
+    def __init__(self, params, stream=None):
+        p = np.ascontiguousarray(params, np.float32)
+        ctx = ovl_device_ctx()
+        ctx.stream = stream
+        self.h = C.c_void_p()
+        st = lib().ovl_mlp_create(_p(p), p.size, C.byref(ctx), C.byref(self.h))
+        if st != OK:
+            raise OvlError(st, lib().ovl_mlp_last_error(None).decode())
+
+    def _check(self, st):
+        if st != OK:
+            raise OvlError(st, lib().ovl_mlp_last_error(self.h).decode())
+
+    def step(self, x, t, lr):
+        """One Adam step; x, t are host arrays or torch CUDA tensors."""
+        loss = C.c_float()
+        if hasattr(x, "data_ptr"):
+            self._check(lib().ovl_mlp_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                                 x.shape[0], float(lr), 1, C.byref(loss)))
+        else:
+            X = np.ascontiguousarray(x, np.float32)
+            T = np.ascontiguousarray(t, np.float32)
+            self._check(lib().ovl_mlp_train_step(self.h, _p(X), _p(T), X.shape[0], float(lr), 0, C.byref(loss)))
+        return loss.value
+
+    def gradient(self, x, t):
+        X = np.ascontiguousarray(x, np.float32)
+        T = np.ascontiguousarray(t, np.float32)
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = C.c_float()
+        self._check(lib().ovl_mlp_gradient(self.h, _p(X), _p(T), X.shape[0], 0, _p(g), C.byref(loss)))
+        return loss.value, g
+
+    def params(self):
+        p = np.zeros(MLP_PARAMS, np.float32)
+        self._check(lib().ovl_mlp_get_params(self.h, _p(p), MLP_PARAMS))
+        return p
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().ovl_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

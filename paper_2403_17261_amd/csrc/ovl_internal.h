@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace ovl {
 
 constexpr int kMaxParts = 64;        // partitions per scene (u64 membership mask)
@@ -12,6 +14,12 @@ constexpr int kColStride = kMaxColours + 1;
 constexpr int kPgsBlock = 1024;      // one workgroup per partition
 constexpr int kLdsReps = 4800;       // replicas whose velocities fit in LDS (two float4 each)
 constexpr int kBlock = 256;          // generic per-item kernels
+// warm-start network 12 -> 64 -> 64 -> 3
+constexpr int kMlpIn = 12, kMlpHid = 64, kMlpOut = 3;
+constexpr int kMlpParams = kMlpIn * kMlpHid + kMlpHid + kMlpHid * kMlpHid + kMlpHid + kMlpHid * kMlpOut + kMlpOut;
+constexpr int kMlpWb = 16 * 64 + 64 * 64 + 64 * 16;  // padded bfloat16 weight tiles
+constexpr int kMlpBias = 64 + 64 + 16;
+constexpr int kFeatStride = 16;      // 12 features, impulse scale s, padding
 
 // device scalar slots
 enum Scal {
@@ -132,6 +140,17 @@ struct WP {
   float4* r_lam;                // [Mcap] impulses (3 used)
   float4* r_lam0;               // [Mcap] warm-start impulses
   float4* rep_v4;               // [2*Rcap] velocity storage of partitions too large for LDS
+  // learned warm start
+  int32_t learned;              // 1: learned start for contacts, guarded per partition
+  int32_t feat_on;              // 1: write the per-copy features
+  float* r_feat;                // [Mcap][kFeatStride] uid order
+  float4* r_lamL;               // [Mcap] learned start, slot order
+  const uint16_t* mlp_wb;       // [kMlpWb]
+  const float* mlp_bias;        // [kMlpBias]
+  int32_t* part_guard;          // [G] 1 when the learned start was kept
+  float* part_rho0;             // [G*2] initial residual of the plain and of the learned start
+  const int32_t* part_force_guard;  // [G] -1 decide, 0 plain, 1 learned
+  int32_t force_guard;
   // warm-start cache (uid order of the last committed step)
   int32_t* wc_part;             // [Mcap]
   int32_t* wc_kind;             // [Mcap]
@@ -176,5 +195,7 @@ constexpr int64_t kBytesDynDyn = 220;
 constexpr int64_t kBytesStatic = 164;
 constexpr int64_t kBytesJoint = 192;
 hipError_t pgs_set_attributes();
+hipError_t launch_mlp_world(const WP& w, hipStream_t s);
+void mlp_pack(const float* params, std::vector<uint16_t>& wb, std::vector<float>& bias);
 
 }  // namespace ovl

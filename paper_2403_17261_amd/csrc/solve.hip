@@ -247,6 +247,68 @@ __device__ __forceinline__ int cache_find(const WP& w, int n, int part, int kind
   return -1;
 }
 
+// Features of a contact copy for the learned warm start (joints: zeros).
+// Velocities are those at the start of the solve (v~ = v + h g); the velocity
+// scale is g h and the impulse scale s = g h / (1/m_a + 1/m_b):
+//   n (3), relative contact-point velocity in (n, t1, t2) / (g h) (3),
+//   gap / margin, (1/m_a, 1/m_b) / (1/m_a + 1/m_b) (2), the plain start
+//   (lambda_n, |lambda_t|) / s (2), conflict degree / 16; then s.
+__device__ void write_features(const WP& w, int u, int src, int p, float l0, float l1, float l2) {
+  float* f = w.r_feat + (int64_t)u * kFeatStride;
+  if (src < w.J) {
+    for (int k = 0; k < kFeatStride; ++k) f[k] = 0.0f;
+    return;
+  }
+  const int N = w.N;
+  const int c = src - w.J;
+  const int a = w.c_a[c];
+  const uint32_t bk = w.c_bkey[c];
+  const int b = (bk >> 1) < (uint32_t)N ? (int)(bk >> 1) : -1;
+  const int64_t CC = w.Ccap;
+  const f3 n = mk(w.c_geom[c], w.c_geom[CC + c], w.c_geom[2 * CC + c]);
+  const float phi = w.c_geom[3 * CC + c];
+  const float la = w.c_geom[4 * CC + c], lb = w.c_geom[5 * CC + c];
+  f3 t1, t2;
+  tangents(n, t1, t2);
+  const float h = w.dt;
+  const f3 hg = mk(h * w.gx, h * w.gy, h * w.gz);
+  const f3 va = add(mk(w.st[7 * N + a], w.st[8 * N + a], w.st[9 * N + a]), hg);
+  const f3 wa = mk(w.st[10 * N + a], w.st[11 * N + a], w.st[12 * N + a]);
+  f3 pa = add(va, scale(cross(wa, n), la));
+  f3 pb = mk(0, 0, 0);
+  const float ima = w.b_invm[a];
+  float imb = 0.0f;
+  if (b >= 0) {
+    const f3 vb = add(mk(w.st[7 * N + b], w.st[8 * N + b], w.st[9 * N + b]), hg);
+    const f3 wb = mk(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b]);
+    pb = sub(vb, scale(cross(wb, n), lb));
+    imb = w.b_invm[b];
+  }
+  const f3 vr = sub(pb, pa);
+  const float g = sqrtf(w.gx * w.gx + w.gy * w.gy + w.gz * w.gz);
+  const float vs = g * h > 0.0f ? g * h : 1.0f;
+  const float sim = vs / (ima + imb);
+  const float margin = w.s_margin[w.b_scene[a]];
+  const int* inc_cnt = w.inc_off + w.Rcap;
+  const int r0 = w.part_rep_off[p];
+  int deg = inc_cnt[r0 + w.cp_ia[u]] - 1;
+  if (b >= 0) deg += inc_cnt[r0 + w.cp_ib[u]] - 1;
+  f[0] = n.x;
+  f[1] = n.y;
+  f[2] = n.z;
+  f[3] = dot(vr, n) / vs;
+  f[4] = dot(vr, t1) / vs;
+  f[5] = dot(vr, t2) / vs;
+  f[6] = margin > 0.0f ? phi / margin : phi;
+  f[7] = ima / (ima + imb);
+  f[8] = imb / (ima + imb);
+  f[9] = l0 / sim;
+  f[10] = sqrtf(l1 * l1 + l2 * l2) / sim;
+  f[11] = (float)deg / 16.0f;
+  f[12] = sim;
+  f[13] = f[14] = f[15] = 0.0f;
+}
+
 __global__ void k_rows(WP w) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   const int M = w.part_copy_off[w.G];
@@ -328,6 +390,7 @@ __global__ void k_rows(WP w) {
   }
   w.r_lam0[slot] = make_float4(l0, l1, l2, 0.0f);
   w.r_lam[slot] = make_float4(l0, l1, l2, 0.0f);
+  if (w.feat_on) write_features(w, u, src, p, l0, l1, l2);
 }
 
 // ---------------------------------------------------------- Gauss-Seidel ----
@@ -481,6 +544,93 @@ __device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& r
   if (solve) w.r_lam[slot] = R.lam;
 }
 
+// replica velocities with gravity applied (v~ = v + h g) and inverse masses
+__device__ void load_replicas(const WP& w, float4* V, int r0, int nr) {
+  const int N = w.N;
+  const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
+  for (int r = threadIdx.x; r < nr; r += kPgsBlock) {
+    const int b = w.rep_body_pm[r0 + r];
+    V[2 * r] = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
+    V[2 * r + 1] = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
+  }
+}
+
+// natural-map residual of one copy's three rows at the given velocities
+__device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float cfm) {
+  float vr[3], bias[3], lo[3], hi[3];
+  const float* l = &R.lam.x;
+  if (R.joint) {
+    const f3 ra = mk(R.r0.x, R.r0.y, R.r0.z), rb = mk(R.r1.x, R.r1.y, R.r1.z);
+    const f3 d = sub(add(A.v, cross(A.w, ra)), add(B.v, cross(B.w, rb)));
+    vr[0] = d.x;
+    vr[1] = d.y;
+    vr[2] = d.z;
+    bias[0] = R.r0.w;
+    bias[1] = R.r1.w;
+    bias[2] = R.r2.w;
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = -INFINITY;
+      hi[k] = INFINITY;
+    }
+  } else {
+    const f3 n = mk(R.r0.x, R.r0.y, R.r0.z);
+    f3 t1, t2;
+    tangents_from(n, R.r0.w, t1, t2);
+    const f3 dv = sub(B.v, A.v);
+    const f3 sw = add(scale(A.w, R.r1.x), scale(B.w, R.r1.y));
+    vr[0] = dot(n, dv);
+    vr[1] = dot(t1, dv) - dot(t2, sw);
+    vr[2] = dot(t2, dv) + dot(t1, sw);
+    bias[0] = R.r1.z;
+    bias[1] = bias[2] = 0.0f;
+    lo[0] = 0.0f;
+    hi[0] = INFINITY;
+    hi[1] = hi[2] = R.r1.w * l[0];
+    lo[1] = lo[2] = -hi[1];
+  }
+  const float invd[3] = {R.r2.x, R.r2.y, R.r2.z};
+  float e = 0.0f;
+  for (int k = 0; k < 3; ++k) {
+    const float wv = vr[k] + bias[k] + cfm * l[k];
+    const float pr = fminf(fmaxf(l[k] - wv * invd[k], lo[k]), hi[k]);
+    e = fmaxf(e, fabsf(l[k] - pr) / invd[k]);
+  }
+  return e;
+}
+
+// Initial residual of a start (plain, or learned for contacts): apply it in
+// solve order, take the largest natural-map residual of the partition's rows,
+// then restore v~.  Uniform over the workgroup.
+__device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const int* coff, int r0, int nr,
+                                bool learned, float* red) {
+  const int tid = threadIdx.x;
+  float unused = 0.0f;
+  for (int c = 0; c < ncol; ++c) {
+    const int e = s0 + coff[c + 1];
+    for (int slot = s0 + coff[c] + tid; slot < e; slot += kPgsBlock) {
+      Rec R;
+      load_rec(w, slot, R);
+      if (learned && !R.joint) R.lam = w.r_lamL[slot];
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false>(w, V, R, unused, slot);
+    }
+    __syncthreads();
+  }
+  float e = 0.0f;
+  for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += kPgsBlock) {
+    Rec R;
+    load_rec(w, slot, R);
+    if (learned && !R.joint) R.lam = w.r_lamL[slot];
+    const Bod A = ld_body(V, R.ia);
+    Bod B = {mk(0, 0, 0), mk(0, 0, 0), 0.0f, 0.0f};
+    if (R.ib >= 0) B = ld_body(V, R.ib);
+    e = fmaxf(e, copy_residual(R, A, B, w.cfm));
+  }
+  e = block_max<kPgsBlock>(e, red);
+  load_replicas(w, V, r0, nr);
+  __syncthreads();
+  return e;
+}
+
 template <bool kLds>
 __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   extern __shared__ float4 sm4[];
@@ -507,15 +657,25 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   const int ncol = w.part_ncol[p];
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
   float4* V = kLds ? sm4 : w.rep_v4 + 2 * (int64_t)r0;
-  // replica velocities with gravity applied (v~ = v + h g) and inverse masses
-  const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
-  for (int r = tid; r < nr; r += kPgsBlock) {
-    const int b = w.rep_body_pm[r0 + r];
-    V[2 * r] = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
-    V[2 * r + 1] = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
-  }
+  load_replicas(w, V, r0, nr);
   __syncthreads();
   float rl = 0.0f;
+  if (w.learned) {
+    // keep the learned start only when its initial residual is below the plain start's
+    const float rho_p = start_residual(w, V, s0, ncol, coff, r0, nr, false, red);
+    const float rho_l = start_residual(w, V, s0, ncol, coff, r0, nr, true, red);
+    bool use = rho_l < rho_p;
+    if (w.force_guard && w.part_force_guard[p] >= 0) use = w.part_force_guard[p] != 0;
+    if (use)
+      for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += kPgsBlock)
+        if (!(w.r_ids[slot].x & kJointFlag)) w.r_lam[slot] = w.r_lamL[slot];
+    if (tid == 0) {
+      w.part_guard[p] = use ? 1 : 0;
+      w.part_rho0[2 * p] = rho_p;
+      w.part_rho0[2 * p + 1] = rho_l;
+    }
+    __syncthreads();
+  }
   // warm-start impulses enter in solve order
   for (int c = 0; c < ncol; ++c) {
     const int e = s0 + coff[c + 1];
@@ -790,6 +950,9 @@ hipError_t launch_solve(const WP& w, int32_t* sc, hipStream_t s, bool exact_resi
   if (w.Mcap > 0) {
     k_rows<<<nblocks(w.Mcap, kBlock), kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
+  }
+  if (w.learned) {
+    if ((e = launch_mlp_world(w, s))) return e;
   }
   if (w.G > 0) {
     if (ev_pgs_begin && (e = hipEventRecord(ev_pgs_begin, s))) return e;

@@ -41,6 +41,8 @@ struct ovl_world {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   double pgs_ms = 0.0;
   int64_t pgs_launches = 0;
+  uint16_t* mlp_wb = nullptr;
+  float* mlp_bias = nullptr;
 
   hipEvent_t take_event() {
     if (!ev_pool.empty()) {
@@ -144,6 +146,8 @@ struct ovl_world {
     w.r_lam = alloc<float4>(g, Mcap, ok);
     w.r_lam0 = alloc<float4>(g, Mcap, ok);
     w.rep_v4 = alloc<float4>(g, (size_t)2 * Rcap, ok);
+    w.r_feat = alloc<float>(g, (size_t)kFeatStride * Mcap, ok);
+    w.r_lamL = alloc<float4>(g, Mcap, ok);
     w.wc_part = alloc<int32_t>(g, Mcap, ok);
     w.wc_kind = alloc<int32_t>(g, Mcap, ok);
     w.wc_key = alloc<uint64_t>(g, Mcap, ok);
@@ -169,6 +173,9 @@ struct ovl_world {
     w.part_ncol = alloc<int32_t>(g, G_ + 1, ok);
     w.part_iters = alloc<int32_t>(g, G_ + 1, ok);
     w.part_nstatic = alloc<int32_t>(g, G_ + 1, ok);
+    w.part_guard = alloc<int32_t>(g, G_ + 1, ok);
+    w.part_rho0 = alloc<float>(g, 2 * (size_t)G_ + 2, ok);
+    w.part_force_guard = alloc<int32_t>(g, G_ + 1, ok);
     w.part_resid = alloc<float>(g, G_ + 1, ok);
     return ok;
   }
@@ -283,6 +290,7 @@ ovl_status set_partitions_impl(ovl_world* w, const int32_t* owner, const int32_t
     w->free_group(w->part_allocs);
     if (!w->alloc_parts(G)) return w->fail(OVL_ERR_OOM, "partition buffers");
     w->forced_next = false;
+    w->wp.force_guard = 0;
   }
   bool ok = w->upload((void*)w->wp.owner_local, local.data(), N * sizeof(int32_t)) &&
             w->upload((void*)w->wp.s_part_base, base.data(), (S + 1) * sizeof(int32_t)) &&
@@ -630,6 +638,99 @@ ovl_status ovl_step(ovl_world* w, int32_t n_steps, ovl_step_stats* stats, int32_
   return OVL_OK;
 }
 
+ovl_status ovl_set_warmstart(ovl_world* w, int32_t mode, const float* params, int64_t n_params) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  if (mode == OVL_WARM_NONE || mode == OVL_WARM_PLAIN) {
+    w->prm.warmstart = mode;
+    w->wp.warmstart = mode == OVL_WARM_PLAIN;
+    w->wp.learned = 0;
+    return OVL_OK;
+  }
+  if (mode != OVL_WARM_LEARNED) return w->fail(OVL_ERR_INVALID_ARG, "unknown warm-start mode");
+  if (!params || n_params != kMlpParams)
+    return w->fail(OVL_ERR_INVALID_ARG, "learned mode needs OVL_MLP_PARAMS parameters");
+  for (int64_t i = 0; i < n_params; ++i)
+    if (!std::isfinite(params[i])) return w->fail(OVL_ERR_INVALID_ARG, "non-finite network parameter");
+  std::vector<uint16_t> wb;
+  std::vector<float> bias;
+  mlp_pack(params, wb, bias);
+  bool ok = true;
+  if (!w->mlp_wb) {
+    w->mlp_wb = w->alloc<uint16_t>(w->static_allocs, kMlpWb, ok);
+    w->mlp_bias = w->alloc<float>(w->static_allocs, kMlpBias, ok);
+    if (!ok) return w->fail(OVL_ERR_OOM, "network buffers");
+  }
+  if (hipStreamSynchronize(w->stream) != hipSuccess || !w->upload(w->mlp_wb, wb.data(), wb.size() * 2) ||
+      !w->upload(w->mlp_bias, bias.data(), bias.size() * 4) || hipStreamSynchronize(w->stream) != hipSuccess)
+    return w->fail(OVL_ERR_DEVICE, "upload failed");
+  w->wp.mlp_wb = w->mlp_wb;
+  w->wp.mlp_bias = w->mlp_bias;
+  w->prm.warmstart = OVL_WARM_PLAIN;
+  w->wp.warmstart = 1;
+  w->wp.learned = 1;
+  w->wp.feat_on = 1;
+  return OVL_OK;
+}
+
+ovl_status ovl_set_feature_export(ovl_world* w, int32_t enable) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  w->wp.feat_on = (enable != 0 || w->wp.learned) ? 1 : 0;
+  return OVL_OK;
+}
+
+ovl_status ovl_force_guard(ovl_world* w, const int32_t* choice, int32_t n_parts) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  if (!choice) {
+    w->wp.force_guard = 0;
+    return OVL_OK;
+  }
+  if (n_parts != w->G) return w->fail(OVL_ERR_INVALID_ARG, "n_parts differs from the partition count");
+  for (int g = 0; g < n_parts; ++g)
+    if (choice[g] < -1 || choice[g] > 1) return w->fail(OVL_ERR_INVALID_ARG, "choice must be -1, 0 or 1");
+  if (!w->upload((void*)w->wp.part_force_guard, choice, n_parts * sizeof(int32_t)) ||
+      hipStreamSynchronize(w->stream) != hipSuccess)
+    return w->fail(OVL_ERR_DEVICE, "upload failed");
+  w->wp.force_guard = 1;
+  return OVL_OK;
+}
+
+ovl_status ovl_collect_training_rows(ovl_world* w, float* features, float* targets, int64_t capacity_rows,
+                                     int64_t* n_rows) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  if (!w->wp.feat_on) return w->fail(OVL_ERR_INVALID_ARG, "feature export is off");
+  if (hipStreamSynchronize(w->stream) != hipSuccess) return w->fail(OVL_ERR_DEVICE, "sync failed");
+  const WP& p = w->wp;
+  int32_t G = w->G, M = 0;
+  if (hipMemcpy(&M, p.part_copy_off + G, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return w->fail(OVL_ERR_DEVICE, "copy failed");
+  M = std::min(M, p.Mcap);
+  std::vector<int32_t> src(M), slot(M);
+  std::vector<float> feat((size_t)M * kFeatStride);
+  std::vector<float4> lam(p.Mcap);
+  if (M > 0 && (hipMemcpy(src.data(), p.cp_src, M * 4, hipMemcpyDeviceToHost) ||
+                hipMemcpy(slot.data(), p.cp_slot, M * 4, hipMemcpyDeviceToHost) ||
+                hipMemcpy(feat.data(), p.r_feat, feat.size() * 4, hipMemcpyDeviceToHost) ||
+                hipMemcpy(lam.data(), p.r_lam, lam.size() * sizeof(float4), hipMemcpyDeviceToHost)))
+    return w->fail(OVL_ERR_DEVICE, "copy failed");
+  int64_t n = 0;
+  for (int u = 0; u < M; ++u) {
+    if (src[u] < w->J) continue;
+    if (features && targets) {
+      if (n >= capacity_rows) return w->fail(OVL_ERR_INVALID_ARG, "buffers too small");
+      const float* f = &feat[(size_t)u * kFeatStride];
+      for (int k = 0; k < kMlpIn; ++k) features[n * kMlpIn + k] = f[k];
+      const float s_imp = f[12] > 0.0f ? f[12] : 1.0f;
+      const float4 l = lam[slot[u]];
+      targets[n * 3] = l.x / s_imp;
+      targets[n * 3 + 1] = l.y / s_imp;
+      targets[n * 3 + 2] = l.z / s_imp;
+    }
+    ++n;
+  }
+  if (n_rows) *n_rows = n;
+  return OVL_OK;
+}
+
 ovl_status ovl_profile(ovl_world* w, int32_t enable) {
   if (!w) return OVL_ERR_INVALID_ARG;
   w->profiling = enable != 0;
@@ -913,6 +1014,43 @@ extern "C" ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int
       std::vector<int32_t> v;
       ok = dl(w, v, p.part_col_off, (size_t)G * kColStride);
       put(v.data(), (size_t)G * kColStride, 4);
+      break;
+    }
+    case OVL_DBG_COPY_FEAT: {
+      std::vector<float> f;
+      ok = dl(w, f, p.r_feat, (size_t)M * kFeatStride);
+      std::vector<float> o((size_t)13 * M);
+      for (int u = 0; u < M && ok; ++u)
+        for (int k = 0; k < 13; ++k) o[13 * (size_t)u + k] = f[(size_t)u * kFeatStride + k];
+      put(o.data(), (size_t)13 * M, 4);
+      break;
+    }
+    case OVL_DBG_COPY_LAMBDAL: {
+      std::vector<int32_t> slot, src;
+      std::vector<float4> lc, l0;
+      ok = dl(w, slot, p.cp_slot, M) && dl(w, src, p.cp_src, M) && dl(w, lc, (const float4*)p.r_lamL, (size_t)p.Mcap) &&
+           dl(w, l0, (const float4*)p.r_lam0, (size_t)p.Mcap);
+      std::vector<float> o((size_t)3 * M);
+      for (int u = 0; u < M && ok; ++u)
+        if (slot[u] >= 0 && slot[u] < p.Mcap) {
+          const float4 l = src[u] < J ? l0[slot[u]] : lc[slot[u]];
+          o[3 * (size_t)u] = l.x;
+          o[3 * (size_t)u + 1] = l.y;
+          o[3 * (size_t)u + 2] = l.z;
+        }
+      put(o.data(), (size_t)3 * M, 4);
+      break;
+    }
+    case OVL_DBG_PART_GUARD: {
+      std::vector<int32_t> v;
+      ok = dl(w, v, p.part_guard, G);
+      put(v.data(), G, 4);
+      break;
+    }
+    case OVL_DBG_PART_RHO0: {
+      std::vector<float> v;
+      ok = dl(w, v, p.part_rho0, 2 * (size_t)G);
+      put(v.data(), 2 * (size_t)G, 4);
       break;
     }
     default:

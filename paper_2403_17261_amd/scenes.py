@@ -398,3 +398,22 @@ def concat_scenes(scenes: list, name: str = "concat", **kw) -> Scene:
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+
+
+# --------------------------------------------------------------------------------------------
+# Initial weights of the warm-start network (random numbers passed in as inputs)
+# --------------------------------------------------------------------------------------------
+
+MLP_SHAPES = [(12, 64), (64,), (64, 64), (64,), (64, 3), (3,)]
+
+
+def mlp_initial_weights(seed: int = 0) -> np.ndarray:
+    """Flat float32 parameters W1, b1, W2, b2, W3, b3: He-normal weights, zero biases."""
+    rng = _rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            parts.append(rng.normal(0.0, math.sqrt(2.0 / shape[0]), size=shape).reshape(-1))
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)

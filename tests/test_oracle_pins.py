@@ -558,3 +558,87 @@ def test_scenes_are_independent(orc):
     assert np.abs(ob["state"][:64] - oa["state"]).max() < 1e-9
     assert np.abs(ob["state"][64:] - ob_["state"]).max() < 1e-9
     assert len(ob["contact_key"]) == len(oa["contact_key"]) + len(ob_["contact_key"])
+
+
+# ------------------------------------------------------------------------------------------
+# warm-start network reference (training) and its bfloat16 evaluation
+# ------------------------------------------------------------------------------------------
+
+def test_mlp_gradient_matches_finite_differences():
+    from oracle import mlp
+
+    rng = np.random.default_rng(1)
+    p = scenes.mlp_initial_weights(3).astype(np.float64) + rng.normal(0, 0.05, mlp.N_PARAMS)
+    X = rng.normal(size=(7, 12))
+    T = rng.normal(size=(7, 3))
+    loss, g = mlp.loss_and_grad(p, X, T)
+    idx = rng.choice(mlp.N_PARAMS, 60, replace=False)
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = 1e-6
+        fd = (mlp.loss_and_grad(p + e, X, T)[0] - mlp.loss_and_grad(p - e, X, T)[0]) / 2e-6
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+def test_mlp_forward_identity_network():
+    """With identity weights the network passes the (positive) first three inputs through."""
+    from oracle import mlp
+
+    P = {"W1": np.eye(12, 64), "b1": np.zeros(64), "W2": np.eye(64), "b2": np.zeros(64),
+         "W3": np.eye(64, 3), "b3": np.array([0.5, -1.0, 2.0])}
+    X = np.abs(np.random.default_rng(0).normal(size=(5, 12)))
+    y, _ = mlp.forward(mlp.flatten(P), X)
+    assert np.allclose(y, X[:, :3] + P["b3"], atol=1e-15)
+
+
+def test_adam_first_step_moves_by_learning_rate():
+    """At t = 1 Adam's bias-corrected step is lr * g / (|g| + eps) = lr * sign(g)."""
+    from oracle import mlp
+
+    opt = mlp.Adam(4, lr=0.01, eps=0.0)
+    p = np.zeros(4)
+    g = np.array([3.0, -0.5, 1e-3, -7.0])
+    assert np.allclose(opt.step(p, g), -0.01 * np.sign(g), atol=1e-15)
+
+
+def test_bf16_rounding_and_mlp_inference(orc):
+    """bfloat16 rounding is round-to-nearest-even on the top 16 bits; the matrix-engine
+    evaluation equals the float64 network run on bfloat16-rounded values."""
+    from oracle import mlp
+
+    assert orc.bf16(1.0 + 2 ** -9) == 1.0                       # tie to even
+    assert orc.bf16(1.0 + 3 * 2 ** -9) == 1.0 + 2 ** -7
+    assert orc.bf16(-2.0 ** -130) == -2.0 ** -130               # subnormal below the cut stays exact
+    rng = np.random.default_rng(5)
+    P = scenes.mlp_initial_weights(7)
+    X = rng.normal(size=(6, 12))
+    y = orc.mlp_infer(P, X)
+    r = np.vectorize(orc.bf16)
+    Pq = unq = mlp.unflatten(P.astype(np.float64))
+    Xb = r(X.astype(np.float32))
+    h1 = r(np.maximum(Xb @ r(unq["W1"]) + unq["b1"], 0).astype(np.float32))
+    h2 = r(np.maximum(h1 @ r(unq["W2"]) + unq["b2"], 0).astype(np.float32))
+    y2 = h2 @ r(unq["W3"]) + Pq["b3"]
+    assert np.allclose(y, y2, rtol=1e-6, atol=1e-7)
+
+
+def test_learned_start_guard_and_features(orc):
+    """Features of a resting sphere; the guard keeps whichever start has the lower
+    initial residual, so a network that predicts the exact impulse is kept."""
+    h = 1.0 / 60.0
+    sc = scenes.custom_spheres([[0, 0, 0.5]], 0.5, 2.0, planes=scenes.GROUND, dt=h, iters=5)
+    o = orc.step(sc, warmstart=False)
+    f = o["copy_feat"][0]
+    assert np.allclose(f[:3], [0, 0, -1]) and f[3] == pytest.approx(-1.0)        # approaching at g h
+    assert f[7] == 1.0 and f[8] == 0.0 and f[12] == pytest.approx(2.0 * G * h)  # s = m g h
+    # a network whose output bias is exactly lambda_n / s = 1 (all weights zero)
+    P = np.zeros(orc.MLP_PARAMS, np.float32)
+    P[-3] = 1.0
+    o2 = orc.step(sc, warmstart=False, mlp=P, adaptive=True, tol=1e-9, max_iters=50)
+    assert o2["part_guard"][0] == 1
+    assert o2["part_rho0"][0, 1] < 1e-6 < o2["part_rho0"][0, 0]
+    assert o2["part_iters"][0] == 1
+    bad = P.copy()
+    bad[-3] = 5.0                      # five times too large: the plain (zero) start wins
+    o3 = orc.step(sc, warmstart=False, mlp=bad, adaptive=True, tol=1e-9, max_iters=50)
+    assert o3["part_guard"][0] == 0
