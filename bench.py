@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--cap", type=int, default=1000)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm", choices=["plain", "learned", "both"], default="both",
+                    help="warm start of the timed run; 'both' times plain then learned and reports learned")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2403_17261_amd", "data", "warmstart_mlp.npz"))
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -151,41 +154,65 @@ def main():
     mode = ovl.MODE_ADAPTIVE if args.mode == "adaptive" else ovl.MODE_FIXED
     cap = args.cap if mode == ovl.MODE_ADAPTIVE else sc.iters
     p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN)
-    w = ovl.World(sc, p)
     owner0 = sc.owner.copy()
     cent0 = sc.centroids[0].copy() if sc.rebalance_every else None
-    w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
-    log(f"warm-up: {args.warmup} steps")
-    run_loop(w, sc, args.warmup, sc.state, owner0, cent0)
-    w.sync()
-    # reset to the scene's initial state: the timed steps are the run's first `steps` steps
-    w.write_state(sc.state, keep_cache=False)
-    w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
-    w.profile(True)
-    c0 = w.counters()
-    log(f"timed: {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_loop(w, sc, args.steps, sc.state, owner0, cent0)
-    w.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    c1 = w.counters()
-    last = w.step(0, stats=True)
-    secs = t1 - t0
-    steps_done = c1["steps"] - c0["steps"]
-    if steps_done != args.steps:
-        raise RuntimeError(f"only {steps_done} of {args.steps} steps committed")
-    pgs_ms = c1["pgs_ms"] - c0["pgs_ms"]
-    pgs_launches = c1["pgs_launches"] - c0["pgs_launches"]
-    pgs_bytes = c1["pgs_bytes"] - c0["pgs_bytes"]
-    achieved = pgs_bytes / (pgs_ms * 1e-3) / 1e9 if pgs_ms > 0 else 0.0
+    weights = None
+    modes = ["plain", "learned"] if args.warm == "both" else [args.warm]
+    if "learned" in modes:
+        if os.path.exists(args.weights):
+            weights = np.load(args.weights, allow_pickle=False)["params"]
+        else:
+            log(f"no network weights at {args.weights}: timing the plain warm start only")
+            modes = ["plain"]
+    runs = {}
+    for mode_name in modes:
+        w = ovl.World(sc, p)
+        w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        if mode_name == "learned":
+            w.set_warmstart(ovl.WARM_LEARNED, weights)
+        log(f"[{mode_name}] warm-up: {args.warmup} steps")
+        run_loop(w, sc, args.warmup, sc.state, owner0, cent0)
+        w.sync()
+        # reset to the scene's initial state: the timed steps are the run's first `steps` steps
+        w.write_state(sc.state, keep_cache=False)
+        w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        w.profile(True)
+        c0 = w.counters()
+        log(f"[{mode_name}] timed: {args.steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_loop(w, sc, args.steps, sc.state, owner0, cent0)
+        w.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c1 = w.counters()
+        last = w.step(0, stats=True)
+        secs = t1 - t0
+        steps_done = c1["steps"] - c0["steps"]
+        if steps_done != args.steps:
+            raise RuntimeError(f"only {steps_done} of {args.steps} steps committed")
+        r = {"secs": secs, "value": sc.n_bodies * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
+             "pgs_ms": c1["pgs_ms"] - c0["pgs_ms"], "pgs_launches": c1["pgs_launches"] - c0["pgs_launches"],
+             "pgs_bytes": c1["pgs_bytes"] - c0["pgs_bytes"],
+             "sweeps_mean": (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / max(1, steps_done),
+             "sweeps_part_mean": (c1["sweeps_part_total"] - c0["sweeps_part_total"]) / max(1, steps_done * w.G),
+             "unconverged": c1["unconverged_total"] - c0["unconverged_total"], "last": last}
+        r["achieved"] = r["pgs_bytes"] / (r["pgs_ms"] * 1e-3) / 1e9 if r["pgs_ms"] > 0 else 0.0
+        runs[mode_name] = r
+        log(f"[{mode_name}] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step, solver "
+            f"{r['pgs_ms'] / max(1, r['pgs_launches']):.3f} ms/launch, {r['achieved']:.1f} GB/s algorithmic, "
+            f"sweeps/step {r['sweeps_mean']:.1f} (partition mean {r['sweeps_part_mean']:.1f}), "
+            f"unconverged {r['unconverged']}")
+        w.close()
+    head = runs["learned"] if "learned" in runs else runs["plain"]
+    secs = head["secs"]
+    pgs_ms, pgs_launches, pgs_bytes = head["pgs_ms"], head["pgs_launches"], head["pgs_bytes"]
+    achieved = head["achieved"]
     traffic = measured_traffic()
-    sweeps_mean = (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / max(1, steps_done)
-    unconv = c1["unconverged_total"] - c0["unconverged_total"]
-    value = sc.n_bodies * args.steps / secs
-    log(f"{value:.3e} body-steps/s, {1e3 * secs / args.steps:.3f} ms/step, solver {pgs_ms / max(1, pgs_launches):.3f} "
-        f"ms/launch, {achieved:.1f} GB/s algorithmic, mean sweeps {sweeps_mean:.1f}, unconverged {unconv}")
+    sweeps_mean = head["sweeps_mean"]
+    unconv = head["unconverged"]
+    last = head["last"]
+    value = head["value"]
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle steps")
@@ -211,7 +238,13 @@ def main():
                          f"h 1/60 s, 8 k-means partitions (recomputed every 10 steps), 2-hop overlap, beta 4, "
                          f"first {args.steps} steps from the initial drop"),
             "n_bodies": sc.n_bodies, "partitions": int(sc.parts_per_scene[0]), "halo_k": sc.halo_k,
-            "beta": sc.beta, "sweeps": f"{args.mode}, tol {args.tol}, cap {cap}", "warm_start": "plain",
+            "beta": sc.beta, "sweeps": f"{args.mode}, tol {args.tol}, cap {cap}",
+            "warm_start": "learned (guarded per partition)" if "learned" in runs else "plain",
+            "learned_vs_plain": {k: {"body_steps_per_s": v["value"], "ms_per_step": v["ms_per_step"],
+                                     "sweeps_per_step": round(v["sweeps_mean"], 2),
+                                     "partition_sweeps_per_step": round(v["sweeps_part_mean"], 2),
+                                     "unconverged_partition_steps": int(v["unconverged"])}
+                                 for k, v in runs.items()},
             "mean_sweeps_per_step": round(sweeps_mean, 2), "unconverged_partition_steps": int(unconv),
             "last_step": {k: last[k] for k in ("n_contacts", "n_copies", "n_replicas", "n_overlap",
                                                "max_colours")},
