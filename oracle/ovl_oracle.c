@@ -208,6 +208,151 @@ static int sphere_plane(const float* xa, float ra, const float* pl, float margin
   return 1;
 }
 
+/* Capsules (shape 1): a segment of half-length hl along the body z axis,
+ * swept by the radius.  Reading: the world axis is computed from the float
+ * quaternion in double without renormalisation, in this exact order, so every
+ * implementation gets the same bits:
+ *   u = (2 (qx qz + qw qy), 2 (qy qz - qw qx), 1 - 2 (qx qx + qy qy)). */
+static void capsule_axis(const float* q, double* u) {
+  double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  double s;
+  s = qx * qz;
+  s = s + qw * qy;
+  u[0] = 2.0 * s;
+  s = qy * qz;
+  s = s - qw * qx;
+  u[1] = 2.0 * s;
+  s = qx * qx;
+  s = s + qy * qy;
+  u[2] = 1.0 - 2.0 * s;
+}
+
+static double clamp_sym(double x, double h) { return x < -h ? -h : (x > h ? h : x); }
+
+/* Closest points of two segments x_a + s u_a (|s| <= ha) and x_b + t u_b
+ * (|t| <= hb); ha or hb may be 0 (a sphere centre).  Minimising
+ * |r + s u_a - t u_b|^2 with r = x_a - x_b gives the 2x2 system
+ *   a s - b t = -c,   -b s + e t = f
+ * (a = u_a.u_a, e = u_b.u_b, b = u_a.u_b, c = u_a.r, f = u_b.r).  s is taken
+ * from it and clamped, t follows from s and is clamped, and s is recomputed
+ * when t was clamped.  Reading for (near-)parallel segments, where the system
+ * is singular: s is the middle of the stretch of A that B's projection covers
+ * (or the nearest end of A when they do not overlap). */
+static void segment_closest(const double* xa, const double* ua, double ha, const double* xb, const double* ub,
+                            double hb, double* s_out, double* t_out) {
+  double r[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
+  double s = 0.0, t = 0.0;
+  if (ha > 0.0 && hb > 0.0) {
+    double a = dot3(ua, ua), e = dot3(ub, ub), b = dot3(ua, ub);
+    double c = dot3(ua, r), f = dot3(ub, r);
+    double den = a * e - b * b;
+    if (den > 1e-9 * (a * e)) {
+      s = clamp_sym((b * f - c * e) / den, ha);
+    } else {
+      double w = fabs(b) * hb;
+      double lo = (-w - c) / a, hi = (w - c) / a;
+      double l2 = lo > -ha ? lo : -ha, h2 = hi < ha ? hi : ha;
+      s = l2 <= h2 ? 0.5 * (l2 + h2) : clamp_sym(-c / a, ha);
+    }
+    t = (b * s + f) / e;
+    if (t < -hb || t > hb) {
+      t = clamp_sym(t, hb);
+      s = clamp_sym((b * t - c) / a, ha);
+    }
+  } else if (hb > 0.0) {
+    t = clamp_sym(dot3(ub, r) / dot3(ub, ub), hb);
+  } else if (ha > 0.0) {
+    s = clamp_sym(-dot3(ua, r) / dot3(ua, ua), ha);
+  }
+  *s_out = s;
+  *t_out = t;
+}
+
+/* Contact of two swept segments (at least one a capsule, or a capsule and a
+ * static sphere).  Same gap test as for spheres, on the closest points; the
+ * lever arms point at the midpoint of the two surface points:
+ *   r_a = s u_a + (ra + phi/2) n,   r_b = t u_b - (rb + phi/2) n. */
+static int swept_pair(const float* xa_f, const double* ua, double ha, float ra_f, const float* xb_f,
+                      const double* ub, double hb, float rb_f, float margin, contact* out) {
+  double xa[3] = {xa_f[0], xa_f[1], xa_f[2]}, xb[3] = {xb_f[0], xb_f[1], xb_f[2]};
+  double s, t;
+  segment_closest(xa, ua, ha, xb, ub, hb, &s, &t);
+  double pa[3], pb[3];
+  for (int k = 0; k < 3; ++k) {
+    pa[k] = xa[k] + s * ua[k];
+    pb[k] = xb[k] + t * ub[k];
+  }
+  double dx = pb[0] - pa[0];
+  double dy = pb[1] - pa[1];
+  double dz = pb[2] - pa[2];
+  double d2 = dx * dx;
+  d2 = d2 + dy * dy;
+  d2 = d2 + dz * dz;
+  double sr = (double)ra_f + (double)rb_f;
+  sr = sr + (double)margin;
+  if (!(d2 < sr * sr)) return 0;
+  double dist = sqrt(d2);
+  if (d2 > 0.0) {
+    out->n[0] = dx / dist;
+    out->n[1] = dy / dist;
+    out->n[2] = dz / dist;
+  } else {
+    out->n[0] = 0.0;
+    out->n[1] = 0.0;
+    out->n[2] = 1.0;
+  }
+  out->phi = dist - (double)ra_f - (double)rb_f;
+  double la = (double)ra_f + 0.5 * out->phi, lb = (double)rb_f + 0.5 * out->phi;
+  for (int k = 0; k < 3; ++k) {
+    out->ra[k] = s * ua[k] + la * out->n[k];
+    out->rb[k] = t * ub[k] - lb * out->n[k];
+  }
+  return 1;
+}
+
+/* Capsule against a plane: each end of the segment is tested like a sphere
+ * centre (sub 0 for the end at -hl, sub 1 for +hl). */
+static int capsule_plane_end(const float* xa_f, const double* u, double hl, float ra, int sub, const float* pl,
+                             float margin, contact* out) {
+  double e[3];
+  for (int k = 0; k < 3; ++k) {
+    double hu = hl * u[k];
+    e[k] = sub ? (double)xa_f[k] + hu : (double)xa_f[k] - hu;
+  }
+  double sd = (double)pl[0] * e[0];
+  sd = sd + (double)pl[1] * e[1];
+  sd = sd + (double)pl[2] * e[2];
+  sd = sd - (double)pl[3];
+  double phi = sd - (double)ra;
+  if (!(phi < (double)margin)) return 0;
+  out->phi = phi;
+  for (int k = 0; k < 3; ++k) {
+    out->n[k] = -(double)pl[k];
+    out->ra[k] = (sub ? hl : -hl) * u[k] + ((double)ra + 0.5 * phi) * out->n[k];
+    out->rb[k] = 0.0;
+  }
+  return 1;
+}
+
+/* any pair of dynamic bodies: the sphere test when both are spheres */
+static int body_pair(const orc_scene* sc, const float* st, int64_t a, int64_t b, contact* out) {
+  float m = sc->margin[sc->scene[a]];
+  const float* xa = st + 13 * a;
+  const float* xb = st + 13 * b;
+  if (sc->shape[a] == 0 && sc->shape[b] == 0) return sphere_sphere(xa, sc->radius[a], xb, sc->radius[b], m, out);
+  double ua[3] = {0, 0, 0}, ub[3] = {0, 0, 0};
+  double ha = 0.0, hb = 0.0;
+  if (sc->shape[a] == 1) {
+    capsule_axis(xa + 3, ua);
+    ha = sc->halflen[a];
+  }
+  if (sc->shape[b] == 1) {
+    capsule_axis(xb + 3, ub);
+    hb = sc->halflen[b];
+  }
+  return swept_pair(xa, ua, ha, sc->radius[a], xb, ub, hb, sc->radius[b], m, out);
+}
+
 typedef struct {
   int64_t* k;
   int64_t n;
@@ -234,16 +379,32 @@ static void static_contacts(const orc_scene* sc, int64_t a, const float* xa, int
   int s = sc->scene[a];
   float m = sc->margin[s];
   contact c;
-  for (int64_t j = sc->plane_off[s]; j < sc->plane_off[s + 1]; ++j)
-    if (sphere_plane(xa, sc->radius[a], sc->planes + 4 * j, m, &c)) {
-      c.key = contact_key(a, sc->n_bodies + j, 0);
-      cl_push(out, &c);
+  const int cap = sc->shape[a] == 1;
+  double u[3] = {0, 0, 0}, zero[3] = {0, 0, 0};
+  if (cap) capsule_axis(xa + 3, u);
+  for (int64_t j = sc->plane_off[s]; j < sc->plane_off[s + 1]; ++j) {
+    if (!cap) {
+      if (sphere_plane(xa, sc->radius[a], sc->planes + 4 * j, m, &c)) {
+        c.key = contact_key(a, sc->n_bodies + j, 0);
+        cl_push(out, &c);
+      }
+      continue;
     }
-  for (int64_t j = sc->ssph_off[s]; j < sc->ssph_off[s + 1]; ++j)
-    if (sphere_sphere(xa, sc->radius[a], sc->ssph + 4 * j, sc->ssph[4 * j + 3], m, &c)) {
+    for (int sub = 0; sub < 2; ++sub)
+      if (capsule_plane_end(xa, u, sc->halflen[a], sc->radius[a], sub, sc->planes + 4 * j, m, &c)) {
+        c.key = contact_key(a, sc->n_bodies + j, sub);
+        cl_push(out, &c);
+      }
+  }
+  for (int64_t j = sc->ssph_off[s]; j < sc->ssph_off[s + 1]; ++j) {
+    const float* cs = sc->ssph + 4 * j;
+    int hit = cap ? swept_pair(xa, u, sc->halflen[a], sc->radius[a], cs, zero, 0.0, cs[3], m, &c)
+                  : sphere_sphere(xa, sc->radius[a], cs, cs[3], m, &c);
+    if (hit) {
       c.key = contact_key(a, sc->n_bodies + P + j, 0);
       cl_push(out, &c);
     }
+  }
 }
 
 typedef struct {
@@ -285,7 +446,7 @@ static void find_contacts(const orc_scene* sc, const float* st, const pairset* j
       for (int64_t b = a + 1; b < N && sc->scene[b] == sc->scene[a]; ++b) {
         contact c;
         if (jointed(js, a, b)) continue;
-        if (sphere_sphere(st + 13 * a, sc->radius[a], st + 13 * b, sc->radius[b], sc->margin[sc->scene[a]], &c)) {
+        if (body_pair(sc, st, a, b, &c)) {
           c.key = contact_key(a, b, 0);
           cl_push(&tmp, &c);
         }
@@ -295,10 +456,13 @@ static void find_contacts(const orc_scene* sc, const float* st, const pairset* j
       for (int64_t i = 0; i < tmp.n; ++i) cl_push(out, &tmp.c[i]);
     }
   } else {
-    /* the oracle's own uniform grid: cells of edge 2*r_max + margin_max */
+    /* the oracle's own uniform grid: cells of edge 2*r_max + margin_max, with
+     * r the bounding radius (radius + half-length for a capsule) */
     double rmax = 0.0, mmax = 0.0;
-    for (int64_t i = 0; i < N; ++i)
-      if (sc->radius[i] > rmax) rmax = sc->radius[i];
+    for (int64_t i = 0; i < N; ++i) {
+      double rb = (double)sc->radius[i] + (sc->shape[i] == 1 ? (double)sc->halflen[i] : 0.0);
+      if (rb > rmax) rmax = rb;
+    }
     for (int s = 0; s < sc->n_scenes; ++s)
       if (sc->margin[s] > mmax) mmax = sc->margin[s];
     double cs = 2.0 * rmax + mmax;
@@ -326,8 +490,7 @@ static void find_contacts(const orc_scene* sc, const float* st, const pairset* j
               int64_t b = e[i].body;
               contact c;
               if (b <= a || jointed(js, a, b)) continue;
-              if (sphere_sphere(st + 13 * a, sc->radius[a], st + 13 * b, sc->radius[b], sc->margin[sc->scene[a]],
-                                &c)) {
+              if (body_pair(sc, st, a, b, &c)) {
                 c.key = contact_key(a, b, 0);
                 cl_push(&tmp, &c);
               }
@@ -669,7 +832,8 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
   const int32_t G = pbase[S];
   for (int64_t i = 0; i < N; ++i) {
     int s = sc->scene[i];
-    if (sc->shape[i] != 0 || owner[i] < pbase[s] || owner[i] >= pbase[s + 1]) {
+    int bad_shape = sc->shape[i] != 0 && !(sc->shape[i] == 1 && sc->halflen[i] > 0.0f);
+    if (bad_shape || owner[i] < pbase[s] || owner[i] >= pbase[s + 1]) {
       snprintf(res->err, sizeof res->err, "body %lld: bad shape or owner", (long long)i);
       stats[6] = 1;
       free(pbase);

@@ -22,7 +22,7 @@ extern "C" {
 typedef struct {
   int32_t n_bodies, n_scenes, n_joints;
   const int32_t* scene;        /* [N] nondecreasing */
-  const int32_t* shape;        /* [N] 0 = sphere */
+  const int32_t* shape;        /* [N] 0 = sphere, 1 = capsule along body z (halflen > 0) */
   const float* radius;         /* [N] */
   const float* halflen;        /* [N] */
   const float* mass;           /* [N] */

@@ -103,6 +103,20 @@ def capsule_mass_inertia(radius: float, halflen: float, density: float):
     return mc + ms, np.array([ixx, ixx, izz], dtype=np.float64)
 
 
+def capsule_inertia_for_mass(mass: float, radius: float, halflen: float) -> np.ndarray:
+    """Principal moments of a uniform solid capsule of the given mass."""
+    m1, i1 = capsule_mass_inertia(radius, halflen, 1.0)
+    return (i1 * (float(mass) / m1)).astype(np.float32)
+
+
+def random_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniformly distributed unit quaternions (w, x, y, z): normalised 4-D Gaussians, w >= 0."""
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q[q[:, 0] < 0] *= -1.0
+    return q.astype(np.float32)
+
+
 def _identity_state(pos: np.ndarray) -> np.ndarray:
     n = pos.shape[0]
     st = np.zeros((n, 13), dtype=np.float32)
@@ -269,6 +283,55 @@ def bowl_scene(n: int, seed: int, n_parts: int, scale: float = 1.0, mu: float = 
     return blk
 
 
+def capsule_pile(n: int, seed: int, n_parts: int, frac: float = 0.5, scale: float = 1.0, mu: float = 0.6,
+                 rmin=0.15, rmax=0.35, hmin=0.15, hmax=0.45, density=1000.0) -> Scene:
+    """Bowl pile of mixed spheres and capsules, random orientations.
+
+    Each body is a capsule with probability `frac` (radius U(rmin, rmax),
+    half-length U(hmin, hmax)), else a sphere of radius U(rmin, rmax).  Bodies
+    start on a jittered lattice whose spacing exceeds twice the largest
+    bounding radius (radius + half-length) plus the margin, so none overlap.
+    """
+    rng = _rng(seed)
+    margin = 0.05 * rmin
+    R = rmax + hmax
+    spacing = 2.0 * R + margin + 0.05
+    hx, z0 = 19.5 * scale, 1.0
+    gx = np.arange(-hx + R, hx - R + 1e-9, spacing)
+    if gx.size == 0:
+        gx = np.zeros(1)
+    per_layer = gx.size * gx.size
+    nz = -(-n // per_layer) + 1
+    gz = z0 + R + spacing * np.arange(nz)
+    sites = rng.choice(per_layer * nz, size=n, replace=False)
+    iz, rem = np.divmod(sites, per_layer)
+    iy, ix = np.divmod(rem, gx.size)
+    pos = np.stack([gx[ix], gx[iy], gz[iz]], 1)
+    pos = pos + rng.uniform(-0.02, 0.02, size=pos.shape)
+    radius = rng.uniform(rmin, rmax, size=n)
+    is_cap = rng.uniform(size=n) < frac
+    hl = np.where(is_cap, rng.uniform(hmin, hmax, size=n), 0.0)
+    mass = np.empty(n)
+    inertia = np.empty((n, 3))
+    for i in range(n):
+        if is_cap[i]:
+            mass[i], inertia[i] = capsule_mass_inertia(radius[i], hl[i], density)
+        else:
+            mass[i] = density * 4.0 / 3.0 * math.pi * radius[i] ** 3
+            inertia[i] = 0.4 * mass[i] * radius[i] ** 2
+    st = _identity_state(pos.astype(np.float32))
+    st[:, 3:7] = random_quaternions(rng, n)
+    blk = dict(shape=is_cap.astype(np.int32), radius=radius.astype(np.float32), halflen=hl.astype(np.float32),
+               mass=mass.astype(np.float32), inertia=inertia.astype(np.float32), state=st)
+    owner, cent = kmeans_owner(st[:, :3], n_parts, seed=seed)
+    blk.update(planes=bowl_planes(20.0 * scale), mu=mu, margin=np.float32(margin), owner=owner,
+               n_parts=int(n_parts))
+    sc = _assemble([blk], f"capsule-pile-{n}-seed{seed}", halo_k=2, beta=4, dt=1 / 60, iters=30, steps=300,
+                   rebalance_every=10)
+    sc.centroids = [cent]
+    return sc
+
+
 def config2(seed: int = 0, n: int = 20000) -> Scene:
     """Bowl pile: spheres r ~ U(0.2, 0.5), density 1000, in a five-plane bowl, 8 k-means parts."""
     blk = bowl_scene(n, seed, 8)
@@ -362,11 +425,18 @@ def chain_line(n: int, n_parts: int = 2, split: Optional[list] = None, radius=0.
 
 def custom_spheres(pos, radius, mass, vel=None, omega=None, planes=None, ssph=None, mu=0.5,
                    margin=None, owner=None, n_parts=1, joint_ab=None, joint_anchor=None, quat=None,
-                   **kw) -> Scene:
-    """Hand-placed spheres (small test problems)."""
+                   halflen=None, **kw) -> Scene:
+    """Hand-placed spheres (small test problems).  Bodies with halflen > 0 are
+    capsules along their body z axis, with the solid-capsule inertia of their mass."""
     pos = np.asarray(pos, np.float32).reshape(-1, 3)
     n = pos.shape[0]
     blk = _sphere_block(pos, radius, mass)
+    if halflen is not None:
+        hl = np.broadcast_to(np.asarray(halflen, np.float32), (n,)).copy()
+        for i in np.nonzero(hl > 0)[0]:
+            blk["shape"][i] = 1
+            blk["halflen"][i] = hl[i]
+            blk["inertia"][i] = capsule_inertia_for_mass(blk["mass"][i], blk["radius"][i], hl[i])
     if vel is not None:
         blk["state"][:, 7:10] = np.asarray(vel, np.float32).reshape(-1, 3)
     if omega is not None:
