@@ -50,18 +50,19 @@ typedef enum {
 typedef struct ovl_world ovl_world;
 
 /* Scene content of a world (section 4: the set of non-static bodies plus
- * static bodies of infinite mass).  Only spheres (shape 0) with isotropic
- * inertia are accepted by this version. */
+ * static bodies of infinite mass).  Bodies are spheres (shape 0, isotropic
+ * inertia) or capsules (shape 1: the segment of half-length halflen along the
+ * body z axis swept by the radius; inertia symmetric about body z). */
 typedef struct {
   int32_t n_bodies;            /* N >= 0 */
   int32_t n_scenes;            /* S >= 1 */
   int32_t n_joints;            /* J >= 0 */
   const int32_t* scene;        /* [N] scene id, nondecreasing */
-  const int32_t* shape;        /* [N] 0 = sphere */
+  const int32_t* shape;        /* [N] 0 = sphere, 1 = capsule */
   const float* radius;         /* [N] > 0 */
-  const float* halflen;        /* [N] unused for spheres (may be NULL) */
+  const float* halflen;        /* [N] capsule half-length > 0; unused for spheres (may be NULL without capsules) */
   const float* mass;           /* [N] > 0 */
-  const float* inertia;        /* [N*3] body-frame principal moments (all three equal) */
+  const float* inertia;        /* [N*3] body-frame principal moments (sphere: all equal; capsule: I_x = I_y) */
   const float* state;          /* [N*13] initial states */
   const float* mu;             /* [S] Coulomb friction coefficient (section 3, Eq. 5-7) */
   const float* margin;         /* [S] contact margin: a pair is in contact when its gap < margin */
@@ -125,8 +126,9 @@ typedef struct {
 /* Create a world from a scene description.  Every body starts in partition 0
  * of its scene (one partition per scene) until ovl_set_partitions is called.
  * On success *out owns all device buffers until ovl_destroy_world.
- * Errors: INVALID_ARG (bad sizes, non-sphere shapes, anisotropic inertia,
- * joints across scenes or unsorted), OOM, DEVICE. */
+ * Errors: INVALID_ARG (bad sizes, a shape other than 0 or 1, a capsule without
+ * a positive half-length, sphere inertia not isotropic or capsule inertia not
+ * symmetric about body z, joints across scenes or unsorted), OOM, DEVICE. */
 ovl_status ovl_create_world(const ovl_world_desc* desc, const ovl_params* params, const ovl_device_ctx* ctx,
                             ovl_world** out);
 
@@ -175,7 +177,9 @@ ovl_status ovl_synchronize(ovl_world* w);
  * (a NULL dst only queries the count).  Synchronises.  Fields and layouts:
  *   CONTACT_KEY   u64 [C]  (a<<32)|(bcode<<1)|sub, sorted; bcode = b for a
  *                          body b > a, N + plane index, N + P + sphere index
- *   CONTACT_GEOM  f32 [C*10] n(3), phi, ra(3), rb(3)
+ *   CONTACT_GEOM  f32 [C*8]  n(3), phi, l_a, l_b, s_a, t_b: the lever arms to the contact
+ *                           point are r_a = s_a u_a + l_a n and r_b = t_b u_b - l_b n, with u the
+ *                           body z axis at the start of the step (s_a = t_b = 0 for spheres)
  *   ADJ_OFF       i32 [N+1]; ADJ i32 [adj_off[N]] (per vertex sorted, unique,
  *                          padded slots hold -1)
  *   MASK          u64 [N]  local partition bits of every body

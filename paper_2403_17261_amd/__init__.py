@@ -29,7 +29,7 @@ DBG_FIELDS = ["contact_key", "contact_geom", "adj_off", "adj", "mask", "part_rep
               "part_copy_off", "copy_kind", "copy_key", "copy_ia", "copy_ib", "copy_colour", "copy_lambda0",
               "copy_lambda", "rep_state", "part_iters", "part_resid", "cache_part", "cache_kind", "cache_key",
               "cache_val", "part_col_off", "copy_feat", "copy_lambdal", "part_guard", "part_rho0"]
-_DBG_DTYPE = {"contact_key": (np.uint64, 1), "contact_geom": (np.float32, 10), "mask": (np.uint64, 1),
+_DBG_DTYPE = {"contact_key": (np.uint64, 1), "contact_geom": (np.float32, 8), "mask": (np.uint64, 1),
               "rep_w": (np.float32, 1), "copy_key": (np.uint64, 1), "copy_lambda0": (np.float32, 3),
               "copy_lambda": (np.float32, 3), "rep_state": (np.float32, 13), "part_resid": (np.float32, 1),
               "cache_key": (np.uint64, 1), "cache_val": (np.float32, 4), "copy_feat": (np.float32, 13),

@@ -60,7 +60,10 @@ struct WP {
   const int32_t* b_scene;
   const float* b_radius;
   const float* b_invm;
-  const float* b_invI;
+  const float* b_invI;          // spheres: 1/I; capsules: 1/I_perp (about a transverse axis)
+  const float* b_half;          // capsule half-length (0 for a sphere)
+  const float* b_dI;            // capsules: 1/I_axis - 1/I_perp (0 for a sphere)
+  int32_t has_caps;             // 1 when some body is a capsule
   // scenes
   const float* s_mu;
   const float* s_margin;
@@ -93,7 +96,8 @@ struct WP {
   int32_t* coff;                // [N+1]
   uint32_t* c_bkey;             // [Ccap] (bcode<<1)|sub
   int32_t* c_a;                 // [Ccap]
-  float* c_geom;                // [6][Ccap]: n(3), phi, l_a, l_b (lever arms l_a n and -l_b n)
+  float* c_geom;                // [8][Ccap]: n(3), phi, l_a, l_b, s_a, t_b: lever arms
+                                //   r_a = s_a u_a + l_a n, r_b = t_b u_b - l_b n (u: capsule axis)
   // graph
   int32_t* deg;                 // [N+1]
   int32_t* adj_off;             // [N+1]
@@ -135,8 +139,12 @@ struct WP {
   // rows (slot order = colour-sorted within each partition)
   //   contact: rec0 = (n, a_duff), rec1 = (l_a, l_b, bias_n, mu), rec2 = (1/A_n, 1/A_t1, 1/A_t2, 0)
   //   joint:   rec0 = (r_a, bias_x), rec1 = (r_b, bias_y), rec2 = (1/A_x, 1/A_y, 1/A_z, bias_z)
+  //   contact touching a capsule (kGenFlag): rec1 = (0, 0, bias_n, mu), and r_gen holds the
+  //   full lever arms (r_a, 0), (r_b, 0)
   float4* r_rec;                // [3][Mcap]
-  int2* r_ids;                  // [Mcap] (local replica a | kJointFlag for joints, local replica b or -1)
+  float4* r_gen;                // [2][Mcap] (only with capsules)
+  int2* r_ids;                  // [Mcap] (local replica a | kJointFlag | kGenFlag, local replica b or -1)
+  float4* rep_ax;               // [Rcap] capsule axis u and 1/I_axis - 1/I_perp of each replica
   float4* r_lam;                // [Mcap] impulses (3 used)
   float4* r_lam0;               // [Mcap] warm-start impulses
   float4* rep_v4;               // [2*Rcap] velocity storage of partitions too large for LDS
@@ -169,6 +177,7 @@ struct WP {
 };
 
 constexpr int32_t kJointFlag = 0x40000000;
+constexpr int32_t kGenFlag = 0x20000000;    // a row touching a capsule: full lever arms and inertia
 
 inline int nblocks(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 

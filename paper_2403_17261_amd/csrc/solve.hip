@@ -78,6 +78,29 @@ __device__ __forceinline__ f3 quat_rotate(float qw, float qx, float qy, float qz
   return mk(dot(r0, v), dot(r1, v), dot(r2, v));
 }
 
+// capsule axis u = R(q) e_z of body b from the canonical state
+__device__ __forceinline__ f3 body_axis(const WP& w, int b) {
+  const int N = w.N;
+  return quat_rotate(w.st[3 * N + b], w.st[4 * N + b], w.st[5 * N + b], w.st[6 * N + b], mk(0.0f, 0.0f, 1.0f));
+}
+
+// world inverse inertia of an axisymmetric body applied to x:
+// I^-1 x = x / I_perp + (1/I_axis - 1/I_perp) (u.x) u
+__device__ __forceinline__ f3 inv_inertia(float ii, f3 u, float dI, f3 x) {
+  return add(scale(x, ii), scale(u, dI * dot(u, x)));
+}
+
+// lever arms of contact c: r_a = s_a u_a + l_a n, r_b = t_b u_b - l_b n
+__device__ __forceinline__ void contact_arms(const WP& w, int c, int a, int b, f3 n, f3& ra, f3& rb) {
+  const int64_t CC = w.Ccap;
+  const float la = w.c_geom[4 * CC + c], lb = w.c_geom[5 * CC + c];
+  const float sa = w.c_geom[6 * CC + c], tb = w.c_geom[7 * CC + c];
+  ra = scale(n, la);
+  rb = scale(n, -lb);
+  if (sa != 0.0f) ra = add(ra, scale(body_axis(w, a), sa));
+  if (tb != 0.0f && b >= 0) rb = add(rb, scale(body_axis(w, b), tb));
+}
+
 __device__ __forceinline__ bool prio_gt(uint32_t ha, int ua, uint32_t hb, int ub) {
   return ha > hb || (ha == hb && ua > ub);
 }
@@ -267,21 +290,22 @@ __device__ void write_features(const WP& w, int u, int src, int p, float l0, flo
   const int64_t CC = w.Ccap;
   const f3 n = mk(w.c_geom[c], w.c_geom[CC + c], w.c_geom[2 * CC + c]);
   const float phi = w.c_geom[3 * CC + c];
-  const float la = w.c_geom[4 * CC + c], lb = w.c_geom[5 * CC + c];
+  f3 ra, rb;
+  contact_arms(w, c, a, b, n, ra, rb);
   f3 t1, t2;
   tangents(n, t1, t2);
   const float h = w.dt;
   const f3 hg = mk(h * w.gx, h * w.gy, h * w.gz);
   const f3 va = add(mk(w.st[7 * N + a], w.st[8 * N + a], w.st[9 * N + a]), hg);
   const f3 wa = mk(w.st[10 * N + a], w.st[11 * N + a], w.st[12 * N + a]);
-  f3 pa = add(va, scale(cross(wa, n), la));
+  f3 pa = add(va, cross(wa, ra));
   f3 pb = mk(0, 0, 0);
   const float ima = w.b_invm[a];
   float imb = 0.0f;
   if (b >= 0) {
     const f3 vb = add(mk(w.st[7 * N + b], w.st[8 * N + b], w.st[9 * N + b]), hg);
     const f3 wb = mk(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b]);
-    pb = sub(vb, scale(cross(wb, n), lb));
+    pb = add(vb, cross(wb, rb));
     imb = w.b_invm[b];
   }
   const f3 vr = sub(pb, pa);
@@ -335,15 +359,31 @@ __global__ void k_rows(WP w) {
     const f3 C = add(dx, sub(ra, rb));
     const float k = w.erp / w.dt;
     const float ima = w.b_invm[a], iia = w.b_invI[a], imb = w.b_invm[b], iib = w.b_invI[b];
-    // rows along -e_x, -e_y, -e_z: |r x e_k|^2 = |r|^2 - r_k^2
-    const float raa = dot(ra, ra), rbb = dot(rb, rb);
-    const float Ax = ima + imb + iia * (raa - ra.x * ra.x) + iib * (rbb - rb.x * rb.x) + w.cfm;
-    const float Ay = ima + imb + iia * (raa - ra.y * ra.y) + iib * (rbb - rb.y * rb.y) + w.cfm;
-    const float Az = ima + imb + iia * (raa - ra.z * ra.z) + iib * (rbb - rb.z * rb.z) + w.cfm;
+    float Ax, Ay, Az;
+    const bool gen = w.has_caps && (w.b_half[a] > 0.0f || w.b_half[b] > 0.0f);
+    if (!gen) {
+      // rows along -e_x, -e_y, -e_z: |r x e_k|^2 = |r|^2 - r_k^2
+      const float raa = dot(ra, ra), rbb = dot(rb, rb);
+      Ax = ima + imb + iia * (raa - ra.x * ra.x) + iib * (rbb - rb.x * rb.x) + w.cfm;
+      Ay = ima + imb + iia * (raa - ra.y * ra.y) + iib * (rbb - rb.y * rb.y) + w.cfm;
+      Az = ima + imb + iia * (raa - ra.z * ra.z) + iib * (rbb - rb.z * rb.z) + w.cfm;
+    } else {
+      const f3 ua = body_axis(w, a), ub = body_axis(w, b);
+      const float dIa = w.b_dI[a], dIb = w.b_dI[b];
+      float Ak[3];
+      for (int e = 0; e < 3; ++e) {
+        const f3 ek = mk(e == 0 ? 1.0f : 0.0f, e == 1 ? 1.0f : 0.0f, e == 2 ? 1.0f : 0.0f);
+        const f3 ca = cross(ra, ek), cb = cross(rb, ek);
+        Ak[e] = ima + imb + dot(ca, inv_inertia(iia, ua, dIa, ca)) + dot(cb, inv_inertia(iib, ub, dIb, cb)) + w.cfm;
+      }
+      Ax = Ak[0];
+      Ay = Ak[1];
+      Az = Ak[2];
+    }
     w.r_rec[slot] = make_float4(ra.x, ra.y, ra.z, k * C.x);
     w.r_rec[MC + slot] = make_float4(rb.x, rb.y, rb.z, k * C.y);
     w.r_rec[2 * MC + slot] = make_float4(1.0f / Ax, 1.0f / Ay, 1.0f / Az, k * C.z);
-    w.r_ids[slot] = make_int2(w.cp_ia[u] | kJointFlag, w.cp_ib[u]);
+    w.r_ids[slot] = make_int2(w.cp_ia[u] | kJointFlag | (gen ? kGenFlag : 0), w.cp_ib[u]);
     if (warm) {
       const int hit = cache_find(w, prevM, p, 0, (uint64_t)src);
       if (hit >= 0) {
@@ -368,13 +408,35 @@ __global__ void k_rows(WP w) {
     const float mu = w.s_mu[w.b_scene[a]];
     const float ima = w.b_invm[a], iia = w.b_invI[a];
     const float imb = b >= 0 ? w.b_invm[b] : 0.0f, iib = b >= 0 ? w.b_invI[b] : 0.0f;
-    // sphere contact: r_a = l_a n, r_b = -l_b n, so r x n = 0 and |r x t|^2 = l^2
-    const float An = ima + imb + w.cfm;
-    const float At = ima + imb + iia * la * la + iib * lb * lb + w.cfm;
-    w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
-    w.r_rec[MC + slot] = make_float4(la, lb, bias, mu);
-    w.r_rec[2 * MC + slot] = make_float4(1.0f / An, 1.0f / At, 1.0f / At, 0.0f);
-    w.r_ids[slot] = make_int2(w.cp_ia[u], b >= 0 ? w.cp_ib[u] : -1);
+    const bool gen = w.has_caps && (w.b_half[a] > 0.0f || (b >= 0 && w.b_half[b] > 0.0f));
+    if (!gen) {
+      // sphere contact: r_a = l_a n, r_b = -l_b n, so r x n = 0 and |r x t|^2 = l^2
+      const float An = ima + imb + w.cfm;
+      const float At = ima + imb + iia * la * la + iib * lb * lb + w.cfm;
+      w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
+      w.r_rec[MC + slot] = make_float4(la, lb, bias, mu);
+      w.r_rec[2 * MC + slot] = make_float4(1.0f / An, 1.0f / At, 1.0f / At, 0.0f);
+      w.r_ids[slot] = make_int2(w.cp_ia[u], b >= 0 ? w.cp_ib[u] : -1);
+    } else {
+      // capsule contact: full lever arms, A_rr = m_a^-1 + m_b^-1 + sum (r x d).I^-1 (r x d)
+      f3 ra, rb;
+      contact_arms(w, c, a, b, n, ra, rb);
+      if (b < 0) rb = mk(0.0f, 0.0f, 0.0f);
+      const f3 ua = body_axis(w, a), ub = b >= 0 ? body_axis(w, b) : mk(0.0f, 0.0f, 0.0f);
+      const float dIa = w.b_dI[a], dIb = b >= 0 ? w.b_dI[b] : 0.0f;
+      const f3 dirs[3] = {n, t1, t2};
+      float Ad[3];
+      for (int e = 0; e < 3; ++e) {
+        const f3 ca = cross(ra, dirs[e]), cb = cross(rb, dirs[e]);
+        Ad[e] = ima + imb + dot(ca, inv_inertia(iia, ua, dIa, ca)) + dot(cb, inv_inertia(iib, ub, dIb, cb)) + w.cfm;
+      }
+      w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
+      w.r_rec[MC + slot] = make_float4(0.0f, 0.0f, bias, mu);
+      w.r_rec[2 * MC + slot] = make_float4(1.0f / Ad[0], 1.0f / Ad[1], 1.0f / Ad[2], 0.0f);
+      w.r_gen[slot] = make_float4(ra.x, ra.y, ra.z, 0.0f);
+      w.r_gen[MC + slot] = make_float4(rb.x, rb.y, rb.z, 0.0f);
+      w.r_ids[slot] = make_int2(w.cp_ia[u] | kGenFlag, b >= 0 ? w.cp_ib[u] : -1);
+    }
     if (warm) {
       const int hit = cache_find(w, prevM, p, 1, ((uint64_t)a << 32) | bk);
       if (hit >= 0) {
@@ -399,10 +461,13 @@ __global__ void k_rows(WP w) {
 
 struct Rec {
   float4 r0, r1, r2, lam;
+  float4 g0, g1;  // capsule rows only: (r_a, 0), (r_b, 0)
   int ia, ib;
-  bool joint;
+  bool joint, gen;
 };
 
+// kCaps: the world has capsules, so a record may carry kGenFlag and full lever arms
+template <bool kCaps>
 __device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R) {
   const int64_t MC = w.Mcap;
   R.r0 = w.r_rec[slot];
@@ -410,9 +475,14 @@ __device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R) {
   R.r2 = w.r_rec[2 * MC + slot];
   const int2 id = w.r_ids[slot];
   R.joint = (id.x & kJointFlag) != 0;
-  R.ia = id.x & ~kJointFlag;
+  R.gen = kCaps && (id.x & kGenFlag) != 0;
+  R.ia = id.x & ~(kJointFlag | kGenFlag);
   R.ib = id.y;
   R.lam = w.r_lam[slot];
+  if (kCaps && R.gen && !R.joint) {
+    R.g0 = w.r_gen[slot];
+    R.g1 = w.r_gen[MC + slot];
+  }
 }
 
 struct Bod {
@@ -497,8 +567,9 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
 // Ball joint, rows along -e_k: J_k v = (v_a + w_a x r_a - v_b - w_b x r_b)_k;
 // the impulse dl of row k moves v_a by +dl/m_a e_k and w_a by +dl I_a^-1 (r_a x e_k),
 // and body b the opposite way.
-template <bool solve>
-__device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl) {
+template <bool solve, bool kGen = false>
+__device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl,
+                                           float4 axA = float4{}, float4 axB = float4{}) {
   const f3 ra = mk(R.r0.x, R.r0.y, R.r0.z), rb = mk(R.r1.x, R.r1.y, R.r1.z);
   const float bias[3] = {R.r0.w, R.r1.w, R.r2.w};
   const float invd[3] = {R.r2.x, R.r2.y, R.r2.z};
@@ -521,13 +592,57 @@ __device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float c
     const f3 e = mk(k == 0 ? 1.0f : 0.0f, k == 1 ? 1.0f : 0.0f, k == 2 ? 1.0f : 0.0f);
     A.v = add(A.v, scale(e, A.im * dl));
     B.v = sub(B.v, scale(e, B.im * dl));
-    A.w = add(A.w, scale(cross(ra, e), A.ii * dl));
-    B.w = sub(B.w, scale(cross(rb, e), B.ii * dl));
+    if (kGen) {
+      A.w = add(A.w, scale(inv_inertia(A.ii, mk(axA.x, axA.y, axA.z), axA.w, cross(ra, e)), dl));
+      B.w = sub(B.w, scale(inv_inertia(B.ii, mk(axB.x, axB.y, axB.z), axB.w, cross(rb, e)), dl));
+    } else {
+      A.w = add(A.w, scale(cross(ra, e), A.ii * dl));
+      B.w = sub(B.w, scale(cross(rb, e), B.ii * dl));
+    }
   }
 }
 
+// Contact touching a capsule: rows d = n, t1, t2 with full lever arms,
+//   J_d v = d.(v_b - v_a) + w_b.(r_b x d) - w_a.(r_a x d),
+// and the impulse dl moves v_a by -dl/m_a d, w_a by -dl I_a^-1 (r_a x d), and
+// body b the opposite way.  axA, axB: (capsule axis, 1/I_axis - 1/I_perp).
 template <bool solve>
-__device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& rl, int slot) {
+__device__ __forceinline__ void gen_contact_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl,
+                                                 float4 axA, float4 axB) {
+  const f3 n = mk(R.r0.x, R.r0.y, R.r0.z);
+  f3 t1, t2;
+  tangents_from(n, R.r0.w, t1, t2);
+  const f3 ra = mk(R.g0.x, R.g0.y, R.g0.z), rb = mk(R.g1.x, R.g1.y, R.g1.z);
+  const f3 ua = mk(axA.x, axA.y, axA.z), ub = mk(axB.x, axB.y, axB.z);
+  const float bias = R.r1.z, mu = R.r1.w;
+  float* l = &lam.x;
+  const float invd[3] = {R.r2.x, R.r2.y, R.r2.z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const f3 d = k == 0 ? n : (k == 1 ? t1 : t2);
+    const f3 ca = cross(ra, d), cb = cross(rb, d);
+    float dl;
+    if (solve) {
+      const float vr = dot(d, sub(B.v, A.v)) + dot(cb, B.w) - dot(ca, A.w);
+      const float wv = vr + (k == 0 ? bias : 0.0f) + cfm * l[k];
+      const float hi = k == 0 ? INFINITY : mu * l[0];
+      const float lo = k == 0 ? 0.0f : -hi;
+      const float nl = fminf(fmaxf(l[k] - wv * invd[k], lo), hi);
+      dl = nl - l[k];
+      l[k] = nl;
+      rl = fmaxf(rl, fabsf(dl) * rcp_fast(invd[k]));
+    } else {
+      dl = l[k];
+    }
+    A.v = sub(A.v, scale(d, A.im * dl));
+    B.v = add(B.v, scale(d, B.im * dl));
+    A.w = sub(A.w, scale(inv_inertia(A.ii, ua, axA.w, ca), dl));
+    B.w = add(B.w, scale(inv_inertia(B.ii, ub, axB.w, cb), dl));
+  }
+}
+
+template <bool solve, bool kCaps = false>
+__device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& rl, int slot, int r0 = 0) {
   Bod A = ld_body(V, R.ia);
   Bod B;
   const bool hasB = R.ib >= 0;
@@ -535,10 +650,18 @@ __device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& r
     B = ld_body(V, R.ib);
   else
     B = {mk(0, 0, 0), mk(0, 0, 0), 0.0f, 0.0f};
-  if (R.joint)
+  if (kCaps && R.gen) {
+    const float4 axA = w.rep_ax[r0 + R.ia];
+    const float4 axB = hasB ? w.rep_ax[r0 + R.ib] : float4{};
+    if (R.joint)
+      joint_rows<solve, true>(R, A, B, w.cfm, R.lam, rl, axA, axB);
+    else
+      gen_contact_rows<solve>(R, A, B, w.cfm, R.lam, rl, axA, axB);
+  } else if (R.joint) {
     joint_rows<solve>(R, A, B, w.cfm, R.lam, rl);
-  else
+  } else {
     contact_rows<solve>(R, A, B, w.cfm, R.lam, rl);
+  }
   st_body(V, R.ia, A);
   if (hasB) st_body(V, R.ib, B);
   if (solve) w.r_lam[slot] = R.lam;
@@ -577,10 +700,17 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
     f3 t1, t2;
     tangents_from(n, R.r0.w, t1, t2);
     const f3 dv = sub(B.v, A.v);
-    const f3 sw = add(scale(A.w, R.r1.x), scale(B.w, R.r1.y));
-    vr[0] = dot(n, dv);
-    vr[1] = dot(t1, dv) - dot(t2, sw);
-    vr[2] = dot(t2, dv) + dot(t1, sw);
+    if (R.gen) {
+      const f3 ra = mk(R.g0.x, R.g0.y, R.g0.z), rb = mk(R.g1.x, R.g1.y, R.g1.z);
+      vr[0] = dot(n, dv) + dot(cross(rb, n), B.w) - dot(cross(ra, n), A.w);
+      vr[1] = dot(t1, dv) + dot(cross(rb, t1), B.w) - dot(cross(ra, t1), A.w);
+      vr[2] = dot(t2, dv) + dot(cross(rb, t2), B.w) - dot(cross(ra, t2), A.w);
+    } else {
+      const f3 sw = add(scale(A.w, R.r1.x), scale(B.w, R.r1.y));
+      vr[0] = dot(n, dv);
+      vr[1] = dot(t1, dv) - dot(t2, sw);
+      vr[2] = dot(t2, dv) + dot(t1, sw);
+    }
     bias[0] = R.r1.z;
     bias[1] = bias[2] = 0.0f;
     lo[0] = 0.0f;
@@ -601,6 +731,7 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
 // Initial residual of a start (plain, or learned for contacts): apply it in
 // solve order, take the largest natural-map residual of the partition's rows,
 // then restore v~.  Uniform over the workgroup.
+template <bool kCaps>
 __device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const int* coff, int r0, int nr,
                                 bool learned, float* red) {
   const int tid = threadIdx.x;
@@ -609,16 +740,16 @@ __device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const 
     const int e = s0 + coff[c + 1];
     for (int slot = s0 + coff[c] + tid; slot < e; slot += kPgsBlock) {
       Rec R;
-      load_rec(w, slot, R);
+      load_rec<kCaps>(w, slot, R);
       if (learned && !R.joint) R.lam = w.r_lamL[slot];
-      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false>(w, V, R, unused, slot);
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, unused, slot, r0);
     }
     __syncthreads();
   }
   float e = 0.0f;
   for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += kPgsBlock) {
     Rec R;
-    load_rec(w, slot, R);
+    load_rec<kCaps>(w, slot, R);
     if (learned && !R.joint) R.lam = w.r_lamL[slot];
     const Bod A = ld_body(V, R.ia);
     Bod B = {mk(0, 0, 0), mk(0, 0, 0), 0.0f, 0.0f};
@@ -631,7 +762,7 @@ __device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const 
   return e;
 }
 
-template <bool kLds>
+template <bool kLds, bool kCaps>
 __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   extern __shared__ float4 sm4[];
   __shared__ int coff[kColStride];
@@ -662,8 +793,8 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   float rl = 0.0f;
   if (w.learned) {
     // keep the learned start only when its initial residual is below the plain start's
-    const float rho_p = start_residual(w, V, s0, ncol, coff, r0, nr, false, red);
-    const float rho_l = start_residual(w, V, s0, ncol, coff, r0, nr, true, red);
+    const float rho_p = start_residual<kCaps>(w, V, s0, ncol, coff, r0, nr, false, red);
+    const float rho_l = start_residual<kCaps>(w, V, s0, ncol, coff, r0, nr, true, red);
     bool use = rho_l < rho_p;
     if (w.force_guard && w.part_force_guard[p] >= 0) use = w.part_force_guard[p] != 0;
     if (use)
@@ -681,8 +812,8 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
     const int e = s0 + coff[c + 1];
     for (int slot = s0 + coff[c] + tid; slot < e; slot += kPgsBlock) {
       Rec R;
-      load_rec(w, slot, R);
-      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false>(w, V, R, rl, slot);
+      load_rec<kCaps>(w, slot, R);
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, rl, slot, r0);
     }
     __syncthreads();
   }
@@ -692,20 +823,20 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   float rho = 0.0f;
   Rec cur;
   bool has_cur = ncol > 0 && coff[0] + tid < coff[1];
-  if (has_cur) load_rec(w, s0 + coff[0] + tid, cur);
+  if (has_cur) load_rec<kCaps>(w, s0 + coff[0] + tid, cur);
   while (it < cap) {
     rl = 0.0f;
     for (int c = 0; c < ncol; ++c) {
       const int cn = c + 1 < ncol ? c + 1 : 0;
       Rec nxt;
       const bool has_nxt = coff[cn] + tid < coff[cn + 1];
-      if (has_nxt) load_rec(w, s0 + coff[cn] + tid, nxt);
-      if (has_cur) do_slot<true>(w, V, cur, rl, s0 + coff[c] + tid);
+      if (has_nxt) load_rec<kCaps>(w, s0 + coff[cn] + tid, nxt);
+      if (has_cur) do_slot<true, kCaps>(w, V, cur, rl, s0 + coff[c] + tid, r0);
       const int e = s0 + coff[c + 1];
       for (int slot = s0 + coff[c] + tid + kPgsBlock; slot < e; slot += kPgsBlock) {
         Rec R;
-        load_rec(w, slot, R);
-        do_slot<true>(w, V, R, rl, slot);
+        load_rec<kCaps>(w, slot, R);
+        do_slot<true, kCaps>(w, V, R, rl, slot, r0);
       }
       __syncthreads();
       cur = nxt;
@@ -747,6 +878,19 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
     w.part_iters[p] = it;
     w.part_resid[p] = rho;
   }
+}
+
+// capsule axis and inertia difference of every replica (read by capsule rows)
+__global__ void k_rep_axis(WP w) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= w.Rcap || w.G <= 0 || r >= w.part_rep_off[w.G] || step_failed(w)) return;
+  const int b = w.rep_body_pm[r];
+  float4 ax = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (w.b_half[b] > 0.0f) {
+    const f3 u = body_axis(w, b);
+    ax = make_float4(u.x, u.y, u.z, w.b_dI[b]);
+  }
+  w.rep_ax[r] = ax;
 }
 
 // ------------------------------------------------------- blend + cache ----
@@ -875,7 +1019,8 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
   float e = 0.0f;
   for (int slot = s0 + threadIdx.x; slot < s1; slot += 256) {
     Rec R;
-    load_rec(w, slot, R);
+    load_rec<true>(w, slot, R);
+    if (!w.has_caps) R.gen = false;
     Bod A, B;
     const int ra_ = r0 + R.ia;
     A.v = mk(w.rst[7 * RC + ra_], w.rst[8 * RC + ra_], w.rst[9 * RC + ra_]);
@@ -907,10 +1052,17 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
       f3 t1, t2;
       tangents_from(n, R.r0.w, t1, t2);
       const f3 dv = sub(B.v, A.v);
-      const f3 sw = add(scale(A.w, R.r1.x), scale(B.w, R.r1.y));
-      vr[0] = dot(n, dv);
-      vr[1] = dot(t1, dv) - dot(t2, sw);
-      vr[2] = dot(t2, dv) + dot(t1, sw);
+      if (R.gen) {
+        const f3 ra = mk(R.g0.x, R.g0.y, R.g0.z), rb = mk(R.g1.x, R.g1.y, R.g1.z);
+        vr[0] = dot(n, dv) + dot(cross(rb, n), B.w) - dot(cross(ra, n), A.w);
+        vr[1] = dot(t1, dv) + dot(cross(rb, t1), B.w) - dot(cross(ra, t1), A.w);
+        vr[2] = dot(t2, dv) + dot(cross(rb, t2), B.w) - dot(cross(ra, t2), A.w);
+      } else {
+        const f3 sw = add(scale(A.w, R.r1.x), scale(B.w, R.r1.y));
+        vr[0] = dot(n, dv);
+        vr[1] = dot(t1, dv) - dot(t2, sw);
+        vr[2] = dot(t2, dv) + dot(t1, sw);
+      }
       bias[0] = R.r1.z;
       bias[1] = bias[2] = 0.0f;
       lo[0] = 0.0f;
@@ -934,9 +1086,11 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
 }  // namespace
 
 hipError_t pgs_set_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_pgs<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_pgs<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      2 * kLdsReps * (int)sizeof(float4));
-  return e;
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_pgs<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             2 * kLdsReps * (int)sizeof(float4));
 }
 
 hipError_t launch_solve(const WP& w, int32_t* sc, hipStream_t s, bool exact_residual, hipEvent_t ev_pgs_begin,
@@ -954,11 +1108,21 @@ hipError_t launch_solve(const WP& w, int32_t* sc, hipStream_t s, bool exact_resi
   if (w.learned) {
     if ((e = launch_mlp_world(w, s))) return e;
   }
+  if (w.has_caps && w.Rcap > 0) {
+    k_rep_axis<<<nblocks(w.Rcap, kBlock), kBlock, 0, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+  }
   if (w.G > 0) {
     if (ev_pgs_begin && (e = hipEventRecord(ev_pgs_begin, s))) return e;
-    k_pgs<true><<<w.G, kPgsBlock, 2 * kLdsReps * sizeof(float4), s>>>(w);
-    if ((e = hipGetLastError())) return e;
-    k_pgs<false><<<w.G, kPgsBlock, 0, s>>>(w);
+    if (w.has_caps) {
+      k_pgs<true, true><<<w.G, kPgsBlock, 2 * kLdsReps * sizeof(float4), s>>>(w);
+      if ((e = hipGetLastError())) return e;
+      k_pgs<false, true><<<w.G, kPgsBlock, 0, s>>>(w);
+    } else {
+      k_pgs<true, false><<<w.G, kPgsBlock, 2 * kLdsReps * sizeof(float4), s>>>(w);
+      if ((e = hipGetLastError())) return e;
+      k_pgs<false, false><<<w.G, kPgsBlock, 0, s>>>(w);
+    }
     if ((e = hipGetLastError())) return e;
     if (ev_pgs_end && (e = hipEventRecord(ev_pgs_end, s))) return e;
   }

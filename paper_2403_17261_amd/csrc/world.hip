@@ -126,7 +126,7 @@ struct ovl_world {
     w.Acap = Acap;
     w.c_bkey = alloc<uint32_t>(g, Ccap, ok);
     w.c_a = alloc<int32_t>(g, Ccap, ok);
-    w.c_geom = alloc<float>(g, (size_t)6 * Ccap, ok);
+    w.c_geom = alloc<float>(g, (size_t)8 * Ccap, ok);
     w.adj = alloc<int32_t>(g, Acap, ok);
     w.rep_D_bm = alloc<int32_t>(g, Rcap, ok);
     w.rep_pm_of_bm = alloc<int32_t>(g, Rcap, ok);
@@ -142,6 +142,8 @@ struct ovl_world {
     w.cp_colour = alloc<int32_t>(g, Mcap, ok);
     w.cp_slot = alloc<int32_t>(g, Mcap, ok);
     w.r_rec = alloc<float4>(g, (size_t)3 * Mcap, ok);
+    w.r_gen = alloc<float4>(g, w.has_caps ? (size_t)2 * Mcap : 1, ok);
+    w.rep_ax = alloc<float4>(g, w.has_caps ? (size_t)Rcap : 1, ok);
     w.r_ids = alloc<int2>(g, Mcap, ok);
     w.r_lam = alloc<float4>(g, Mcap, ok);
     w.r_lam0 = alloc<float4>(g, Mcap, ok);
@@ -333,17 +335,30 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   if (J > 0 && (!d->joint_ab || !d->joint_anchor)) return bad("joint arrays must not be NULL");
   std::vector<int32_t> body_off(S + 1, 0), joint_off(S + 1, 0);
   float rmax = 0.0f, mmax = 0.0f;
+  bool has_caps = false;
   for (int i = 0; i < N; ++i) {
     int s = d->scene[i];
     if (s < 0 || s >= S || (i > 0 && s < d->scene[i - 1])) return bad("scene ids must be nondecreasing in [0,S)");
-    if (d->shape[i] != 0) return bad("only spheres (shape 0) are supported");
+    if (d->shape[i] != 0 && d->shape[i] != 1) return bad("shape must be 0 (sphere) or 1 (capsule)");
     if (!(d->radius[i] > 0.0f) || !std::isfinite(d->radius[i])) return bad("radius must be > 0");
     if (!(d->mass[i] > 0.0f) || !std::isfinite(d->mass[i])) return bad("mass must be > 0");
     const float* I = d->inertia + 3 * (size_t)i;
-    if (!(I[0] > 0.0f) || std::fabs(I[1] - I[0]) > 1e-6f * I[0] || std::fabs(I[2] - I[0]) > 1e-6f * I[0])
-      return bad("inertia must be isotropic and > 0 (body " + std::to_string(i) + ")");
+    float bound = d->radius[i];
+    if (d->shape[i] == 1) {
+      if (!d->halflen || !(d->halflen[i] > 0.0f) || !std::isfinite(d->halflen[i]))
+        return bad("a capsule needs a half-length > 0 (body " + std::to_string(i) + ")");
+      if (!(I[0] > 0.0f) || !(I[2] > 0.0f) || !std::isfinite(I[0]) || !std::isfinite(I[2]) ||
+          std::fabs(I[1] - I[0]) > 1e-6f * I[0])
+        return bad("capsule inertia must be > 0 and symmetric about the body z axis (body " + std::to_string(i) +
+                   ")");
+      bound += d->halflen[i];
+      has_caps = true;
+    } else if (!(I[0] > 0.0f) || !std::isfinite(I[0]) || std::fabs(I[1] - I[0]) > 1e-6f * I[0] ||
+               std::fabs(I[2] - I[0]) > 1e-6f * I[0]) {
+      return bad("sphere inertia must be isotropic and > 0 (body " + std::to_string(i) + ")");
+    }
     body_off[s + 1]++;
-    rmax = std::max(rmax, d->radius[i]);
+    rmax = std::max(rmax, bound);
   }
   if (N > 0 && !finite_all(d->state, (size_t)13 * N)) return bad("state has non-finite values");
   for (int s = 0; s < S; ++s) body_off[s + 1] += body_off[s];
@@ -395,6 +410,7 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   wp.Q = Q;
   wp.T = T;
   wp.cs = std::max(1.02f * (2.0f * rmax + mmax), 1e-3f);
+  wp.has_caps = has_caps ? 1 : 0;
   w->set_params(*params);
   bool ok = true;
   auto& g = w->static_allocs;
@@ -403,6 +419,8 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   float* b_radius = w->alloc<float>(g, Np, ok);
   float* b_invm = w->alloc<float>(g, Np, ok);
   float* b_invI = w->alloc<float>(g, Np, ok);
+  float* b_half = w->alloc<float>(g, Np, ok);
+  float* b_dI = w->alloc<float>(g, Np, ok);
   float* s_mu = w->alloc<float>(g, S, ok);
   float* s_margin = w->alloc<float>(g, S, ok);
   int32_t* s_plane_off = w->alloc<int32_t>(g, S + 1, ok);
@@ -452,16 +470,22 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
     return OVL_ERR_OOM;
   }
   // host-side transforms of the inputs
-  std::vector<float> invm(Np, 0.0f), invI(Np, 0.0f), st_cols((size_t)13 * Np, 0.0f);
+  std::vector<float> invm(Np, 0.0f), invI(Np, 0.0f), half(Np, 0.0f), dI(Np, 0.0f), st_cols((size_t)13 * Np, 0.0f);
   for (int i = 0; i < N; ++i) {
     invm[i] = 1.0f / d->mass[i];
     invI[i] = 1.0f / d->inertia[3 * (size_t)i];
+    if (d->shape[i] == 1) {
+      half[i] = d->halflen[i];
+      dI[i] = 1.0f / d->inertia[3 * (size_t)i + 2] - invI[i];
+    }
     for (int k = 0; k < 13; ++k) st_cols[(size_t)k * N + i] = d->state[13 * (size_t)i + k];
   }
   wp.b_scene = b_scene;
   wp.b_radius = b_radius;
   wp.b_invm = b_invm;
   wp.b_invI = b_invI;
+  wp.b_half = b_half;
+  wp.b_dI = b_dI;
   wp.s_mu = s_mu;
   wp.s_margin = s_margin;
   wp.s_plane_off = s_plane_off;
@@ -478,6 +502,7 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   std::vector<int64_t> zeros64(8, 0);
   ok = w->upload(b_scene, d->scene, N * sizeof(int32_t)) && w->upload(b_radius, d->radius, N * sizeof(float)) &&
        w->upload(b_invm, invm.data(), N * sizeof(float)) && w->upload(b_invI, invI.data(), N * sizeof(float)) &&
+       w->upload(b_half, half.data(), N * sizeof(float)) && w->upload(b_dI, dI.data(), N * sizeof(float)) &&
        w->upload(s_mu, d->mu, S * sizeof(float)) && w->upload(s_margin, d->margin, S * sizeof(float)) &&
        w->upload(s_plane_off, d->plane_off, (S + 1) * sizeof(int32_t)) &&
        w->upload(planes, d->planes, (size_t)4 * P * sizeof(float)) &&
@@ -856,20 +881,11 @@ extern "C" ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int
     }
     case OVL_DBG_CONTACT_GEOM: {
       std::vector<float> gcol;
-      ok = dl(w, gcol, p.c_geom, (size_t)6 * p.Ccap);
-      std::vector<float> g((size_t)10 * C);
-      for (int i = 0; i < C && ok; ++i) {
-        const float n[3] = {gcol[i], gcol[(size_t)p.Ccap + i], gcol[2 * (size_t)p.Ccap + i]};
-        const float la = gcol[4 * (size_t)p.Ccap + i], lb = gcol[5 * (size_t)p.Ccap + i];
-        float* o = &g[10 * (size_t)i];
-        for (int k = 0; k < 3; ++k) {
-          o[k] = n[k];
-          o[4 + k] = la * n[k];
-          o[7 + k] = -lb * n[k];
-        }
-        o[3] = gcol[3 * (size_t)p.Ccap + i];
-      }
-      put(g.data(), (size_t)10 * C, 4);
+      ok = dl(w, gcol, p.c_geom, (size_t)8 * p.Ccap);
+      std::vector<float> g((size_t)8 * C);
+      for (int i = 0; i < C && ok; ++i)
+        for (int k = 0; k < 8; ++k) g[8 * (size_t)i + k] = gcol[(size_t)k * p.Ccap + i];
+      put(g.data(), (size_t)8 * C, 4);
       break;
     }
     case OVL_DBG_ADJ_OFF: {

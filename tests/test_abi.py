@@ -54,7 +54,9 @@ def _desc_with(sc, **over):
 @pytest.mark.parametrize("what,over", [
     ("no scenes", dict(n_scenes=0)),
     ("negative bodies", dict(n_bodies=-1)),
-    ("capsule", "capsule"),
+    ("capsule without half-length", "capsule"),
+    ("unknown shape", "shape2"),
+    ("capsule inertia not symmetric about its axis", "cap_aniso"),
     ("anisotropic inertia", "aniso"),
     ("zero mass", "mass0"),
     ("nan state", "nan"),
@@ -64,6 +66,13 @@ def test_create_world_rejects_bad_input_before_touching_the_device(what, over):
     sc = scenes.config1(0)
     if over == "capsule":
         over = dict(shape=np.r_[1, np.zeros(63)].astype(np.int32))
+    elif over == "shape2":
+        over = dict(shape=np.r_[2, np.zeros(63)].astype(np.int32))
+    elif over == "cap_aniso":
+        I = sc.inertia.copy()
+        I[0, 1] *= 2
+        over = dict(shape=np.r_[1, np.zeros(63)].astype(np.int32), halflen=np.r_[0.3, np.zeros(63)].astype(np.float32),
+                    inertia=I)
     elif over == "aniso":
         I = sc.inertia.copy()
         I[3, 2] *= 2
