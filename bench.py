@@ -11,6 +11,11 @@ residual of 1e-4 m/s with a cap of 1000, 300 steps from the initial state
 --workload bowl: the 20,000-sphere bowl pile (8 k-means partitions recomputed
 every 10 steps, 2-hop overlap), 1000 steps.
 
+--workload batched: 512 independent bowl scenes (log-uniform 200..5000
+spheres, 1..6 k-means partitions each, fixed at the start), 30 sweeps per
+step, all in one world: the autotuned, graph-replayed launch against the
+default launch and against a loop that steps one world per scene.
+
 One GPU only.  Prints one JSON line.  The roofline entry is for the
 Gauss-Seidel kernel: algorithmic bytes of all sweeps of the timed steps (per
 sweep and constraint copy: 220 B for two bodies, 164 B with a static body,
@@ -110,10 +115,105 @@ def cpu_baseline(workload, n_steps, tol, cap):
     }
 
 
+def bench_batched(args):
+    """Many uneven scenes: one batched world (default launch; autotuned + graph) against a per-scene loop."""
+    import torch
+
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    sc = scenes.config4(0)
+    steps = args.steps or 50
+    p = ovl.make_params(dt=sc.dt, max_iters=sc.iters, mode=ovl.MODE_FIXED, warmstart=ovl.WARM_PLAIN)
+    N = sc.n_bodies
+    res = {}
+
+    def timed(step_fn, sync_fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step_fn()
+        sync_fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # one world holding every scene
+    for name in ("default", "tuned"):
+        w = ovl.World(sc, p)
+        w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        w.step(args.warmup)
+        chosen, cand_ms = None, None
+        if name == "tuned":
+            w.set_launch(graph=1)
+            chosen, cand_ms = w.autotune(trials=3)
+            log(f"[batched] autotuner chose {chosen}; candidate ms {np.round(cand_ms, 3).tolist()}")
+        w.sync()
+        w.profile(True)
+        c0 = w.counters()
+        w.profile(False)            # profiled steps bypass the graph; time the launch itself
+        secs = timed(lambda: w.step(1), w.sync)
+        c1 = w.counters()
+        if c1["steps"] - c0["steps"] != steps:
+            raise RuntimeError("not every step committed")
+        res[name] = {"secs": secs, "value": N * steps / secs, "ms_per_step": 1e3 * secs / steps,
+                     "launch": w.get_launch(), "candidates_ms": None if cand_ms is None else
+                     [round(float(x), 4) for x in cand_ms]}
+        log(f"[batched {name}] {res[name]['value']:.3e} body-steps/s, {res[name]['ms_per_step']:.3f} ms/step")
+        w.close()
+    # a loop over one world per scene (default launch, no graph)
+    parts = []
+    off = np.searchsorted(sc.scene, np.arange(sc.n_scenes + 1))
+    poff = np.concatenate([[0], np.cumsum(sc.parts_per_scene)])
+    for s_ in range(sc.n_scenes):
+        a, b = off[s_], off[s_ + 1]
+        sub = scenes.Scene(
+            scene=np.zeros(b - a, np.int32), shape=sc.shape[a:b], radius=sc.radius[a:b], halflen=sc.halflen[a:b],
+            mass=sc.mass[a:b], inertia=sc.inertia[a:b], state=sc.state[a:b], mu=sc.mu[s_:s_ + 1],
+            margin=sc.margin[s_:s_ + 1], plane_off=np.array([0, sc.plane_off[s_ + 1] - sc.plane_off[s_]], np.int32),
+            planes=sc.planes[sc.plane_off[s_]:sc.plane_off[s_ + 1]], ssph_off=np.zeros(2, np.int32),
+            ssph=np.zeros((0, 4), np.float32), joint_ab=np.zeros((0, 2), np.int32),
+            joint_anchor=np.zeros((0, 6), np.float32), owner=(sc.owner[a:b] - poff[s_]).astype(np.int32),
+            parts_per_scene=sc.parts_per_scene[s_:s_ + 1].copy(), name=f"scene{s_}", halo_k=sc.halo_k,
+            beta=sc.beta, dt=sc.dt, iters=sc.iters, steps=sc.steps)
+        wsub = ovl.World(sub, p)
+        wsub.set_partitions(sub.owner, sub.parts_per_scene, halo_k=sub.halo_k, beta=sub.beta)
+        parts.append(wsub)
+    for wsub in parts:
+        wsub.step(args.warmup)
+
+    def step_all():
+        for wsub in parts:
+            wsub.step(1)
+
+    secs = timed(step_all, lambda: [wsub.sync() for wsub in parts])
+    res["per_scene_loop"] = {"secs": secs, "value": N * steps / secs, "ms_per_step": 1e3 * secs / steps}
+    log(f"[per-scene loop] {res['per_scene_loop']['value']:.3e} body-steps/s, "
+        f"{res['per_scene_loop']['ms_per_step']:.3f} ms/step")
+    for wsub in parts:
+        wsub.close()
+    head = res["tuned"]
+    out = {
+        "metric": "body-steps/s, batched scenes, 30 sweeps per step",
+        "value": head["value"], "unit": "body-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": (f"512 bowl scenes, spheres log-uniform 200..5000 per scene ({N} in all), r~U(0.2,0.5) m, "
+                         f"1..6 k-means partitions per scene ({int(sc.parts_per_scene.sum())} in all, fixed), "
+                         f"2-hop overlap, h 1/60 s, 30 sweeps per step, steps {args.warmup + 1}..."
+                         f"{args.warmup + steps} of the drop"),
+            "batched_tuned": res["tuned"], "batched_default": res["default"],
+            "per_scene_loop": res["per_scene_loop"],
+            "speedup_vs_per_scene_loop": res["per_scene_loop"]["secs"] / head["secs"],
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["tower", "bowl"], default="tower")
+    ap.add_argument("--workload", choices=["tower", "bowl", "batched"], default="tower")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", choices=["adaptive", "fixed"], default="adaptive")
@@ -147,6 +247,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
+        return
+    if args.workload == "batched":
+        bench_batched(args)
         return
     sc = scenes.config5(0) if args.workload == "tower" else scenes.config2(0)
     if args.steps is None:

@@ -292,6 +292,47 @@ typedef struct {
 } ovl_counters;
 ovl_status ovl_get_counters(ovl_world* w, ovl_counters* out);
 
+/* ---- launch configuration of the solve, HIP graph replay, autotuner ----
+ * (spec pattern: many uneven scenes and partitions in one persistent,
+ * graph-captured launch with autotuned block and tile sizes)
+ *
+ * pgs_block / pgs_lds_reps: threads per partition workgroup and the number of
+ *   replicas whose velocities the workgroup keeps in LDS (larger partitions
+ *   run in a global-memory variant).  Supported pairs: (1024, 4800),
+ *   (512, 2400), (256, 1200), (256, 2400); default (1024, 4800).
+ * persistent: 0 = one workgroup per partition, largest partitions dispatched
+ *   first; 1 = as many workgroups as fit on the device at once, each taking
+ *   partitions (largest first) from an atomic queue until it is empty.
+ * graph: 1 = ovl_step captures one step into a HIP graph and replays it;
+ *   the graph is captured again whenever a parameter, the partitioning or a
+ *   buffer changes.  Steps that force sweep counts, compute the exact
+ *   residual or are profiled run without the graph.
+ * The configuration changes no result: every configuration computes the
+ * same bits. */
+typedef struct {
+  int32_t pgs_block;
+  int32_t pgs_lds_reps;
+  int32_t persistent;
+  int32_t graph;
+} ovl_launch_cfg;
+
+/* INVALID_ARG for an unsupported pair or a flag other than 0/1. */
+ovl_status ovl_set_launch(ovl_world* w, const ovl_launch_cfg* cfg);
+ovl_status ovl_get_launch(const ovl_world* w, ovl_launch_cfg* cfg);
+/* Writes up to cap candidate configurations the autotuner tries (graph = 0)
+ * into out (may be NULL) and returns their number. */
+int32_t ovl_launch_candidates(ovl_launch_cfg* out, int32_t cap);
+/* Autotuner: runs the contacts, graph, colouring and rows of ONE step, then
+ * times the Gauss-Seidel solve of that step `trials` times (1..100) with each
+ * candidate configuration on the same inputs (the minimum counts), checks
+ * that all candidates produce identical replica states and sweep counts
+ * (DEVICE error otherwise), keeps the fastest (graph flag unchanged) and
+ * finishes the step with it: the world advances by exactly one step.
+ * chosen (nullable) receives the configuration, ms (nullable, n_ms >=
+ * ovl_launch_candidates(NULL, 0)) the time of each candidate in the order of
+ * ovl_launch_candidates.  INVALID_ARG while a forced sweep count is pending. */
+ovl_status ovl_autotune(ovl_world* w, int32_t trials, ovl_launch_cfg* chosen, float* ms, int32_t n_ms);
+
 /* Turn HIP-event timing of the solver kernel on (1) or off (0).  Events are
  * recorded on the world's stream around every Gauss-Seidel launch and summed
  * by ovl_get_counters. */

@@ -78,6 +78,11 @@ class ovl_counters(C.Structure):
                 ("pgs_ms", C.c_double)]
 
 
+class ovl_launch_cfg(C.Structure):
+    _fields_ = [("pgs_block", C.c_int32), ("pgs_lds_reps", C.c_int32), ("persistent", C.c_int32),
+                ("graph", C.c_int32)]
+
+
 _lib = None
 
 
@@ -120,6 +125,10 @@ def lib():
             "ovl_mlp_get_params": (C.c_int, [P, P, C.c_int64]),
             "ovl_mlp_last_error": (C.c_char_p, [P]),
             "ovl_mlp_infer": (C.c_int, [P, C.c_int64, P, C.c_int64, P]),
+            "ovl_set_launch": (C.c_int, [P, C.POINTER(ovl_launch_cfg)]),
+            "ovl_get_launch": (C.c_int, [P, C.POINTER(ovl_launch_cfg)]),
+            "ovl_launch_candidates": (C.c_int32, [P, C.c_int32]),
+            "ovl_autotune": (C.c_int, [P, C.c_int32, C.POINTER(ovl_launch_cfg), P, C.c_int32]),
             "ovl_version": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -139,6 +148,18 @@ def header_symbols():
 
 def ovl_version() -> str:
     return lib().ovl_version().decode()
+
+
+def _cfg_dict(c):
+    return {f: int(getattr(c, f)) for f, _ in ovl_launch_cfg._fields_}
+
+
+def launch_candidates():
+    """The launch configurations the autotuner tries, in its order."""
+    n = lib().ovl_launch_candidates(None, 0)
+    arr = (ovl_launch_cfg * n)()
+    lib().ovl_launch_candidates(C.cast(arr, C.c_void_p), n)
+    return [_cfg_dict(arr[i]) for i in range(n)]
 
 
 def _p(a):
@@ -337,6 +358,24 @@ class World:
 
     def cache(self):
         return {k: self.debug(k) for k in ("cache_part", "cache_kind", "cache_key", "cache_val")}
+
+    def set_launch(self, pgs_block=1024, pgs_lds_reps=4800, persistent=0, graph=0):
+        c = ovl_launch_cfg(int(pgs_block), int(pgs_lds_reps), int(persistent), int(graph))
+        self._check(lib().ovl_set_launch(self.h, C.byref(c)))
+
+    def get_launch(self):
+        c = ovl_launch_cfg()
+        self._check(lib().ovl_get_launch(self.h, C.byref(c)))
+        return _cfg_dict(c)
+
+    def autotune(self, trials=3):
+        """Runs one step while timing every candidate launch configuration on it;
+        keeps the fastest.  Returns (chosen config, {candidate index: ms})."""
+        n = lib().ovl_launch_candidates(None, 0)
+        ms = np.zeros(n, np.float32)
+        c = ovl_launch_cfg()
+        self._check(lib().ovl_autotune(self.h, int(trials), C.byref(c), _p(ms), n))
+        return _cfg_dict(c), ms
 
 
 def ovl_mlp_infer(params, x):

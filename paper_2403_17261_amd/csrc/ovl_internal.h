@@ -11,8 +11,11 @@ namespace ovl {
 constexpr int kMaxParts = 64;        // partitions per scene (u64 membership mask)
 constexpr int kMaxColours = 64;      // colours per partition (u64 used-colour mask)
 constexpr int kColStride = kMaxColours + 1;
-constexpr int kPgsBlock = 1024;      // one workgroup per partition
-constexpr int kLdsReps = 4800;       // replicas whose velocities fit in LDS (two float4 each)
+// Gauss-Seidel launch configurations (threads per partition workgroup, replicas
+// whose velocities fit in LDS, two float4 each): 1, 2, 4 and 2 workgroups per CU
+constexpr int kPgsCfgCount = 4;
+constexpr int kPgsCfgBlock[kPgsCfgCount] = {1024, 512, 256, 256};
+constexpr int kPgsCfgReps[kPgsCfgCount] = {4800, 2400, 1200, 2400};
 constexpr int kBlock = 256;          // generic per-item kernels
 // warm-start network 12 -> 64 -> 64 -> 3
 constexpr int kMlpIn = 12, kMlpHid = 64, kMlpOut = 3;
@@ -164,6 +167,12 @@ struct WP {
   int32_t* wc_kind;             // [Mcap]
   uint64_t* wc_key;             // [Mcap]
   float* wc_val;                // [4][Mcap]
+  // Gauss-Seidel schedule
+  int32_t* part_order;          // [G] partitions by descending copy count
+  int32_t* pgs_queue;           // [2] work counters of the persistent kernels (LDS, global)
+  int32_t pgs_cfg;              // index into kPgsCfg*
+  int32_t pgs_persistent;       // 1: resident workgroups take partitions from the queue
+  int32_t pgs_grid[2];          // resident workgroups of the two persistent kernels
   // per-partition results
   int32_t* part_iters;          // [G]
   int32_t* part_nstatic;        // [G] contact copies with a static body
@@ -194,9 +203,15 @@ size_t scan_scratch_ints(int64_t n);
 hipError_t launch_collide(const WP& w, int32_t* scan_scratch, hipStream_t s);
 // graph, overlap sets, replicas, geodesic distances, constraint copies
 hipError_t launch_graph(const WP& w, int32_t* scan_scratch, hipStream_t s);
-// colouring, rows, warm start, projected Gauss-Seidel, integration, blending, cache
-hipError_t launch_solve(const WP& w, int32_t* scan_scratch, hipStream_t s, bool exact_residual,
-                        hipEvent_t ev_pgs_begin = nullptr, hipEvent_t ev_pgs_end = nullptr);
+// solve of a step in three phases: (1) partition order, colouring, rows, warm
+// start; (2) projected Gauss-Seidel with integration of the replicas; (3) exact
+// residual (optional), blending, warm-start cache, commit
+hipError_t launch_solve_pre(const WP& w, hipStream_t s);
+hipError_t launch_pgs(const WP& w, hipStream_t s, hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+hipError_t launch_solve_post(const WP& w, hipStream_t s, bool exact_residual);
+hipError_t pgs_occupancy(int cfg, bool caps, int* per_cu_lds, int* per_cu_glob);
+hipError_t launch_reset_lambda(const WP& w, hipStream_t s);
+hipError_t launch_digest(const WP& w, unsigned long long* out, hipStream_t s);
 
 // Algorithmic bytes of one Gauss-Seidel sweep per constraint copy: the row
 // record and impulses plus the two bodies' velocity read/write and mass data.

@@ -27,6 +27,8 @@
 //    replicas in ascending partition id, quaternions sign-aligned with the
 //    first one and renormalised.  A body with one replica keeps its state.
 #include "ovl_internal.h"
+
+#include <algorithm>
 #include "wave.h"
 
 namespace ovl {
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   __shared__ int running[kMaxColours];
   __shared__ int wcnt[kColWaves][kMaxColours];
   __shared__ int any_s;
-  const int p = blockIdx.x;
+  const int p = w.part_order[blockIdx.x];  // largest partitions first
   const int tid = threadIdx.x;
   if (tid == 0) any_s = (w.scal[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP)) ? 1 : 0;
   __syncthreads();
@@ -668,10 +670,11 @@ __device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& r
 }
 
 // replica velocities with gravity applied (v~ = v + h g) and inverse masses
+template <int BS>
 __device__ void load_replicas(const WP& w, float4* V, int r0, int nr) {
   const int N = w.N;
   const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
-  for (int r = threadIdx.x; r < nr; r += kPgsBlock) {
+  for (int r = threadIdx.x; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
     V[2 * r] = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
     V[2 * r + 1] = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
@@ -731,14 +734,14 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
 // Initial residual of a start (plain, or learned for contacts): apply it in
 // solve order, take the largest natural-map residual of the partition's rows,
 // then restore v~.  Uniform over the workgroup.
-template <bool kCaps>
+template <int BS, bool kCaps>
 __device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const int* coff, int r0, int nr,
                                 bool learned, float* red) {
   const int tid = threadIdx.x;
   float unused = 0.0f;
   for (int c = 0; c < ncol; ++c) {
     const int e = s0 + coff[c + 1];
-    for (int slot = s0 + coff[c] + tid; slot < e; slot += kPgsBlock) {
+    for (int slot = s0 + coff[c] + tid; slot < e; slot += BS) {
       Rec R;
       load_rec<kCaps>(w, slot, R);
       if (learned && !R.joint) R.lam = w.r_lamL[slot];
@@ -747,7 +750,7 @@ __device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const 
     __syncthreads();
   }
   float e = 0.0f;
-  for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += kPgsBlock) {
+  for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += BS) {
     Rec R;
     load_rec<kCaps>(w, slot, R);
     if (learned && !R.joint) R.lam = w.r_lamL[slot];
@@ -756,49 +759,34 @@ __device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const 
     if (R.ib >= 0) B = ld_body(V, R.ib);
     e = fmaxf(e, copy_residual(R, A, B, w.cfm));
   }
-  e = block_max<kPgsBlock>(e, red);
-  load_replicas(w, V, r0, nr);
+  e = block_max<BS>(e, red);
+  load_replicas<BS>(w, V, r0, nr);
   __syncthreads();
   return e;
 }
 
-template <bool kLds, bool kCaps>
-__global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
-  extern __shared__ float4 sm4[];
-  __shared__ int coff[kColStride];
-  __shared__ float red[kPgsBlock / 64];
-  __shared__ int failed_s;
-  const int p = blockIdx.x;
+// Solve one partition with a workgroup of BS threads.  V holds its replica
+// velocities (LDS, or its slice of rep_v4 for the global variant).
+template <int BS, bool kCaps>
+__device__ void solve_partition(const WP& w, int p, float4* V, int* coff, float* red) {
   const int tid = threadIdx.x;
-  // one read of the failure flag per workgroup, so the early exit is uniform
-  if (tid == 0) failed_s = step_failed(w) ? 1 : 0;
-  __syncthreads();
-  if (failed_s) {
-    if (tid == 0) {
-      w.part_iters[p] = 0;
-      w.part_resid[p] = 0.0f;
-    }
-    return;
-  }
   const int N = w.N;
   const int r0 = w.part_rep_off[p];
   const int nr = w.part_rep_off[p + 1] - r0;
-  if (kLds != (nr <= kLdsReps)) return;  // the other variant handles this partition
   const int s0 = w.part_copy_off[p];
   const int ncol = w.part_ncol[p];
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
-  float4* V = kLds ? sm4 : w.rep_v4 + 2 * (int64_t)r0;
-  load_replicas(w, V, r0, nr);
+  load_replicas<BS>(w, V, r0, nr);
   __syncthreads();
   float rl = 0.0f;
   if (w.learned) {
     // keep the learned start only when its initial residual is below the plain start's
-    const float rho_p = start_residual<kCaps>(w, V, s0, ncol, coff, r0, nr, false, red);
-    const float rho_l = start_residual<kCaps>(w, V, s0, ncol, coff, r0, nr, true, red);
+    const float rho_p = start_residual<BS, kCaps>(w, V, s0, ncol, coff, r0, nr, false, red);
+    const float rho_l = start_residual<BS, kCaps>(w, V, s0, ncol, coff, r0, nr, true, red);
     bool use = rho_l < rho_p;
     if (w.force_guard && w.part_force_guard[p] >= 0) use = w.part_force_guard[p] != 0;
     if (use)
-      for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += kPgsBlock)
+      for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += BS)
         if (!(w.r_ids[slot].x & kJointFlag)) w.r_lam[slot] = w.r_lamL[slot];
     if (tid == 0) {
       w.part_guard[p] = use ? 1 : 0;
@@ -810,7 +798,7 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   // warm-start impulses enter in solve order
   for (int c = 0; c < ncol; ++c) {
     const int e = s0 + coff[c + 1];
-    for (int slot = s0 + coff[c] + tid; slot < e; slot += kPgsBlock) {
+    for (int slot = s0 + coff[c] + tid; slot < e; slot += BS) {
       Rec R;
       load_rec<kCaps>(w, slot, R);
       if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, rl, slot, r0);
@@ -833,7 +821,7 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
       if (has_nxt) load_rec<kCaps>(w, s0 + coff[cn] + tid, nxt);
       if (has_cur) do_slot<true, kCaps>(w, V, cur, rl, s0 + coff[c] + tid, r0);
       const int e = s0 + coff[c + 1];
-      for (int slot = s0 + coff[c] + tid + kPgsBlock; slot < e; slot += kPgsBlock) {
+      for (int slot = s0 + coff[c] + tid + BS; slot < e; slot += BS) {
         Rec R;
         load_rec<kCaps>(w, slot, R);
         do_slot<true, kCaps>(w, V, R, rl, slot, r0);
@@ -842,14 +830,14 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
       cur = nxt;
       has_cur = has_nxt;
     }
-    rho = block_max<kPgsBlock>(rl, red);
+    rho = block_max<BS>(rl, red);
     ++it;
     if (!w.forced && w.adaptive && rho <= w.tol) break;
   }
   // integrate and write the replica states
   const float h = w.dt;
   bool bad = false;
-  for (int r = tid; r < nr; r += kPgsBlock) {
+  for (int r = tid; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
     const Bod B = ld_body(V, r);
     const float x = w.st[b] + h * B.v.x;
@@ -877,6 +865,74 @@ __global__ __launch_bounds__(kPgsBlock) void k_pgs(WP w) {
   if (tid == 0) {
     w.part_iters[p] = it;
     w.part_resid[p] = rho;
+  }
+  __syncthreads();  // coff and red are reused by the workgroup's next partition
+}
+
+// Projected Gauss-Seidel over the partitions, largest first (part_order).
+// kLds: velocities in LDS, for the partitions with at most kReps replicas;
+// otherwise velocities in global memory, for the larger ones.  Either one
+// workgroup per partition, or (w.pgs_persistent) a grid of resident
+// workgroups that take partitions from an atomic queue until it is empty.
+template <int BS, int kReps, bool kLds, bool kCaps>
+__global__ __launch_bounds__(BS) void k_pgs(WP w) {
+  extern __shared__ float4 sm4[];
+  __shared__ int coff[kColStride];
+  __shared__ float red[BS / 64];
+  __shared__ int failed_s, item_s;
+  const int tid = threadIdx.x;
+  // one read of the failure flag per workgroup, so the early exit is uniform
+  if (tid == 0) failed_s = step_failed(w) ? 1 : 0;
+  __syncthreads();
+  if (failed_s) {
+    for (int p = blockIdx.x * BS + tid; p < w.G; p += gridDim.x * BS) {
+      w.part_iters[p] = 0;
+      w.part_resid[p] = 0.0f;
+    }
+    return;
+  }
+  int32_t* queue = w.pgs_queue + (kLds ? 0 : 1);
+  for (int k = blockIdx.x;;) {
+    if (w.pgs_persistent) {
+      if (tid == 0) item_s = atomicAdd(queue, 1);
+      __syncthreads();
+      k = item_s;
+      __syncthreads();
+    }
+    if (k >= w.G) break;
+    const int p = w.part_order[k];
+    const int nr = w.part_rep_off[p + 1] - w.part_rep_off[p];
+    if (kLds == (nr <= kReps)) {  // otherwise the other variant handles this partition
+      float4* V = kLds ? sm4 : w.rep_v4 + 2 * (int64_t)w.part_rep_off[p];
+      solve_partition<BS, kCaps>(w, p, V, coff, red);
+    }
+    if (!w.pgs_persistent) break;
+  }
+}
+
+// Partitions in descending order of constraint copies (ties: ascending id),
+// by counting ranks in one workgroup; more than kOrderMax partitions keep
+// their natural order.
+constexpr int kOrderBS = 1024;
+constexpr int kOrderMax = 8192;
+
+__global__ __launch_bounds__(kOrderBS) void k_part_order(WP w) {
+  __shared__ int key[kOrderMax];
+  const int G = w.G;
+  if (G > kOrderMax) {
+    for (int p = threadIdx.x; p < G; p += kOrderBS) w.part_order[p] = p;
+    return;
+  }
+  for (int p = threadIdx.x; p < G; p += kOrderBS) key[p] = w.part_copy_off[p + 1] - w.part_copy_off[p];
+  __syncthreads();
+  for (int p = threadIdx.x; p < G; p += kOrderBS) {
+    const int kp = key[p];
+    int rank = 0;
+    for (int q = 0; q < G; ++q) {
+      const int kq = key[q];
+      rank += (kq > kp || (kq == kp && q < p)) ? 1 : 0;
+    }
+    w.part_order[rank] = p;
   }
 }
 
@@ -1085,19 +1141,74 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
 
 }  // namespace
 
-hipError_t pgs_set_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_pgs<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     2 * kLdsReps * (int)sizeof(float4));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_pgs<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             2 * kLdsReps * (int)sizeof(float4));
+namespace {
+
+template <int BS, int R>
+hipError_t set_attrs_t() {
+  hipError_t e = hipSuccess;
+  const int lds = 2 * R * (int)sizeof(float4);
+  if ((e = hipFuncSetAttribute((const void*)k_pgs<BS, R, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds)))
+    return e;
+  return hipFuncSetAttribute((const void*)k_pgs<BS, R, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-hipError_t launch_solve(const WP& w, int32_t* sc, hipStream_t s, bool exact_residual, hipEvent_t ev_pgs_begin,
-                        hipEvent_t ev_pgs_end) {
-  (void)sc;
+template <int BS, int R>
+hipError_t occupancy_t(bool caps, int* per_cu_lds, int* per_cu_glob) {
+  const size_t lds = 2 * (size_t)R * sizeof(float4);
+  hipError_t e;
+  if (caps) {
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, true>, BS, lds))) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, true>, BS, 0);
+  }
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, false>, BS, lds))) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, false>, BS, 0);
+}
+
+template <int BS, int R>
+hipError_t launch_pgs_t(const WP& w, hipStream_t s) {
+  const size_t lds = 2 * (size_t)R * sizeof(float4);
+  const int g0 = w.pgs_persistent ? std::min(w.G, w.pgs_grid[0]) : w.G;
+  const int g1 = w.pgs_persistent ? std::min(w.G, w.pgs_grid[1]) : w.G;
+  hipError_t e;
+  if (w.pgs_persistent && (e = fill_i32(w.pgs_queue, 0, 2, s))) return e;
+  if (w.has_caps) {
+    k_pgs<BS, R, true, true><<<g0, BS, lds, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+    k_pgs<BS, R, false, true><<<g1, BS, 0, s>>>(w);
+  } else {
+    k_pgs<BS, R, true, false><<<g0, BS, lds, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+    k_pgs<BS, R, false, false><<<g1, BS, 0, s>>>(w);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t pgs_set_attributes() {
+  hipError_t e;
+  if ((e = set_attrs_t<1024, 4800>())) return e;
+  if ((e = set_attrs_t<512, 2400>())) return e;
+  if ((e = set_attrs_t<256, 1200>())) return e;
+  return set_attrs_t<256, 2400>();
+}
+
+hipError_t pgs_occupancy(int cfg, bool caps, int* per_cu_lds, int* per_cu_glob) {
+  switch (cfg) {
+    case 0: return occupancy_t<1024, 4800>(caps, per_cu_lds, per_cu_glob);
+    case 1: return occupancy_t<512, 2400>(caps, per_cu_lds, per_cu_glob);
+    case 2: return occupancy_t<256, 1200>(caps, per_cu_lds, per_cu_glob);
+    case 3: return occupancy_t<256, 2400>(caps, per_cu_lds, per_cu_glob);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_solve_pre(const WP& w, hipStream_t s) {
   hipError_t e;
   if (w.G > 0) {
+    k_part_order<<<1, kOrderBS, 0, s>>>(w);
+    if ((e = hipGetLastError())) return e;
     k_colour<<<w.G, kColBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
@@ -1112,20 +1223,27 @@ hipError_t launch_solve(const WP& w, int32_t* sc, hipStream_t s, bool exact_resi
     k_rep_axis<<<nblocks(w.Rcap, kBlock), kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
-  if (w.G > 0) {
-    if (ev_pgs_begin && (e = hipEventRecord(ev_pgs_begin, s))) return e;
-    if (w.has_caps) {
-      k_pgs<true, true><<<w.G, kPgsBlock, 2 * kLdsReps * sizeof(float4), s>>>(w);
-      if ((e = hipGetLastError())) return e;
-      k_pgs<false, true><<<w.G, kPgsBlock, 0, s>>>(w);
-    } else {
-      k_pgs<true, false><<<w.G, kPgsBlock, 2 * kLdsReps * sizeof(float4), s>>>(w);
-      if ((e = hipGetLastError())) return e;
-      k_pgs<false, false><<<w.G, kPgsBlock, 0, s>>>(w);
-    }
-    if ((e = hipGetLastError())) return e;
-    if (ev_pgs_end && (e = hipEventRecord(ev_pgs_end, s))) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_pgs(const WP& w, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
+  if (w.G <= 0) return hipSuccess;
+  hipError_t e;
+  if (ev_begin && (e = hipEventRecord(ev_begin, s))) return e;
+  switch (w.pgs_cfg) {
+    case 0: e = launch_pgs_t<1024, 4800>(w, s); break;
+    case 1: e = launch_pgs_t<512, 2400>(w, s); break;
+    case 2: e = launch_pgs_t<256, 1200>(w, s); break;
+    case 3: e = launch_pgs_t<256, 2400>(w, s); break;
+    default: e = hipErrorInvalidValue;
   }
+  if (e) return e;
+  if (ev_end && (e = hipEventRecord(ev_end, s))) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_solve_post(const WP& w, hipStream_t s, bool exact_residual) {
+  hipError_t e;
   if (exact_residual && w.G > 0) {
     if ((e = fill_i32((int32_t*)w.stat_f, 0, 1, s))) return e;
     k_exact_resid<<<w.G, 256, 0, s>>>(w);
@@ -1140,6 +1258,41 @@ hipError_t launch_solve(const WP& w, int32_t* sc, hipStream_t s, bool exact_resi
     if ((e = hipGetLastError())) return e;
   }
   k_commit<<<1, 1, 0, s>>>(w);
+  return hipGetLastError();
+}
+
+// reset the impulses to the warm start (to time the solve again on the same inputs)
+__global__ void k_reset_lambda(WP w) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < w.Mcap) w.r_lam[u] = w.r_lam0[u];
+}
+
+// order-independent 64-bit digest of the replica states and sweep counts
+__global__ void k_digest(WP w, unsigned long long* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int R = w.G > 0 ? w.part_rep_off[w.G] : 0;
+  unsigned long long acc = 0;
+  if (i < R) {
+    for (int k = 0; k < 13; ++k) {
+      const uint32_t bits = __float_as_uint(w.rst[(int64_t)k * w.Rcap + i]);
+      acc += (unsigned long long)fmix32(bits ^ fmix32((uint32_t)(13 * i + k))) << (k & 31);
+    }
+  }
+  if (i < w.G) acc += (unsigned long long)fmix32((uint32_t)w.part_iters[i] ^ 0x9e3779b9u) << 7;
+  if (acc) atomicAdd(out, acc);
+}
+
+hipError_t launch_reset_lambda(const WP& w, hipStream_t s) {
+  if (w.Mcap <= 0) return hipSuccess;
+  k_reset_lambda<<<nblocks(w.Mcap, kBlock), kBlock, 0, s>>>(w);
+  return hipGetLastError();
+}
+
+hipError_t launch_digest(const WP& w, unsigned long long* out, hipStream_t s) {
+  hipError_t e;
+  if ((e = fill_u64((uint64_t*)out, 0, 1, s))) return e;
+  const int n = std::max(w.Rcap, w.G);
+  if (n > 0) k_digest<<<nblocks(n, kBlock), kBlock, 0, s>>>(w, out);
   return hipGetLastError();
 }
 

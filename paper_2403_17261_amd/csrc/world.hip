@@ -37,6 +37,15 @@ struct ovl_world {
   int32_t* scan_scratch = nullptr;
   bool forced_next = false;
   bool profiling = false;
+  // launch configuration, captured step graph
+  ovl_launch_cfg launch{1024, 4800, 0, 0};
+  int n_cu = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  WP graph_wp{};
+  bool graph_valid = false;
+  int64_t graph_captures = 0;
+  unsigned long long* digest = nullptr;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   double pgs_ms = 0.0;
@@ -105,6 +114,8 @@ struct ovl_world {
   ~ovl_world() {
     (void)hipStreamSynchronize(stream);
     drain_events();
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     free_group(part_allocs);
     free_group(cap_allocs);
@@ -179,6 +190,7 @@ struct ovl_world {
     w.part_rho0 = alloc<float>(g, 2 * (size_t)G_ + 2, ok);
     w.part_force_guard = alloc<int32_t>(g, G_ + 1, ok);
     w.part_resid = alloc<float>(g, G_ + 1, ok);
+    w.part_order = alloc<int32_t>(g, G_ + 1, ok);
     return ok;
   }
 
@@ -208,18 +220,74 @@ struct ovl_world {
            hipStreamSynchronize(stream) == hipSuccess;
   }
 
-  hipError_t enqueue_step(bool exact) {
+  hipError_t enqueue_step(hipStream_t s, bool exact, bool timed) {
     hipError_t e;
-    if ((e = launch_collide(wp, scan_scratch, stream))) return e;
-    if ((e = launch_graph(wp, scan_scratch, stream))) return e;
+    if ((e = launch_collide(wp, scan_scratch, s))) return e;
+    if ((e = launch_graph(wp, scan_scratch, s))) return e;
+    if ((e = launch_solve_pre(wp, s))) return e;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (profiling) {
+    if (timed) {
       e0 = take_event();
       e1 = take_event();
       if (e0 && e1) ev_pending.emplace_back(e0, e1);
     }
-    if ((e = launch_solve(wp, scan_scratch, stream, exact, e0, e1))) return e;
+    if ((e = launch_pgs(wp, s, e0, e1))) return e;
+    return launch_solve_post(wp, s, exact);
+  }
+
+  // Capture one step (as the parameters stand) into a graph.  The parameter
+  // block is baked into the kernel nodes, so the graph is captured again
+  // whenever it changes (new buffers, parameters, partitions, modes).
+  hipError_t capture() {
+    hipError_t e;
+    if (!cap_stream && (e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking))) return e;
+    if (gexec) {
+      (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+    graph_valid = false;
+    if ((e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal))) return e;
+    hipError_t le = enqueue_step(cap_stream, false, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap_stream, &g);
+    if (le) e = le;
+    if (e) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e) {
+      gexec = nullptr;
+      return e;
+    }
+    graph_wp = wp;
+    graph_valid = true;
+    ++graph_captures;
     return hipSuccess;
+  }
+
+  hipError_t run_one(bool exact) {
+    if (launch.graph && !wp.forced && !exact && !profiling) {
+      if (!graph_valid || memcmp(&graph_wp, &wp, sizeof(WP)) != 0) {
+        hipError_t e = capture();
+        if (e) return e;
+      }
+      return hipGraphLaunch(gexec, stream);
+    }
+    return enqueue_step(stream, exact, profiling);
+  }
+
+  // apply a launch configuration (validated by the caller)
+  bool apply_launch(const ovl_launch_cfg& c, int cfg) {
+    int per_lds = 0, per_glob = 0;
+    if (pgs_occupancy(cfg, wp.has_caps != 0, &per_lds, &per_glob) != hipSuccess) return false;
+    launch = c;
+    wp.pgs_cfg = cfg;
+    wp.pgs_persistent = c.persistent ? 1 : 0;
+    wp.pgs_grid[0] = std::max(1, per_lds) * std::max(1, n_cu);
+    wp.pgs_grid[1] = std::max(1, per_glob) * std::max(1, n_cu);
+    return true;
   }
 
   // Grow every buffer whose count exceeded its capacity (device counts are exact).
@@ -458,6 +526,8 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   wp.scal = w->alloc<int32_t>(g, SC_COUNT, ok);
   wp.stat_f = w->alloc<float>(g, 4, ok);
   wp.stat_i64 = w->alloc<int64_t>(g, 8, ok);
+  wp.pgs_queue = w->alloc<int32_t>(g, 2, ok);
+  w->digest = w->alloc<unsigned long long>(g, 1, ok);
   const size_t scan_n = std::max<size_t>({(size_t)T + 1, (size_t)N + 1, (size_t)64 * S + 1});
   w->scan_scratch = w->alloc<int32_t>(g, scan_scratch_ints((int64_t)scan_n) + 16, ok);
   const int32_t Ccap = std::max(1024, 8 * N);
@@ -531,6 +601,17 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
     }
     attrs = true;
   }
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      w->n_cu = prop.multiProcessorCount;
+    if (!w->apply_launch(w->launch, 0)) {
+      delete w;
+      g_create_error = "could not query the occupancy of the solver kernels";
+      return OVL_ERR_DEVICE;
+    }
+  }
   // one partition per scene until ovl_set_partitions
   std::vector<int32_t> owner(Np, 0), pps(S, 1);
   for (int i = 0; i < N; ++i) owner[i] = d->scene[i];
@@ -581,7 +662,7 @@ ovl_status ovl_force_iters(ovl_world* w, const int32_t* iters, int32_t n_parts) 
 static ovl_status run_steps(ovl_world* w, int32_t n, bool exact_last) {
   for (int i = 0; i < n; ++i) {
     w->wp.forced = w->forced_next ? 1 : 0;
-    hipError_t e = w->enqueue_step(exact_last && i == n - 1);
+    hipError_t e = w->run_one(exact_last && i == n - 1);
     w->wp.forced = 0;
     w->forced_next = false;
     if (e != hipSuccess) return w->fail(OVL_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -753,6 +834,131 @@ ovl_status ovl_collect_training_rows(ovl_world* w, float* features, float* targe
     ++n;
   }
   if (n_rows) *n_rows = n;
+  return OVL_OK;
+}
+
+static int find_pgs_cfg(int32_t block, int32_t reps) {
+  for (int k = 0; k < kPgsCfgCount; ++k)
+    if (kPgsCfgBlock[k] == block && kPgsCfgReps[k] == reps) return k;
+  return -1;
+}
+
+ovl_status ovl_set_launch(ovl_world* w, const ovl_launch_cfg* cfg) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  if (!cfg) return w->fail(OVL_ERR_INVALID_ARG, "cfg is NULL");
+  const int k = find_pgs_cfg(cfg->pgs_block, cfg->pgs_lds_reps);
+  if (k < 0) return w->fail(OVL_ERR_INVALID_ARG, "unsupported (pgs_block, pgs_lds_reps) pair");
+  if ((cfg->persistent != 0 && cfg->persistent != 1) || (cfg->graph != 0 && cfg->graph != 1))
+    return w->fail(OVL_ERR_INVALID_ARG, "persistent and graph must be 0 or 1");
+  if (hipStreamSynchronize(w->stream) != hipSuccess) return w->fail(OVL_ERR_DEVICE, "sync failed");
+  if (!w->apply_launch(*cfg, k)) return w->fail(OVL_ERR_DEVICE, "occupancy query failed");
+  return OVL_OK;
+}
+
+ovl_status ovl_get_launch(const ovl_world* w, ovl_launch_cfg* cfg) {
+  if (!w || !cfg) return OVL_ERR_INVALID_ARG;
+  *cfg = w->launch;
+  return OVL_OK;
+}
+
+int32_t ovl_launch_candidates(ovl_launch_cfg* out, int32_t cap) {
+  int n = 0;
+  for (int k = 0; k < kPgsCfgCount; ++k)
+    for (int pers = 0; pers < 2; ++pers) {
+      if (out && n < cap) out[n] = ovl_launch_cfg{kPgsCfgBlock[k], kPgsCfgReps[k], pers, 0};
+      ++n;
+    }
+  return n;
+}
+
+ovl_status ovl_autotune(ovl_world* w, int32_t trials, ovl_launch_cfg* chosen, float* ms, int32_t n_ms) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  if (trials < 1 || trials > 100) return w->fail(OVL_ERR_INVALID_ARG, "trials must be in [1,100]");
+  if (w->forced_next) return w->fail(OVL_ERR_INVALID_ARG, "a forced sweep count is pending");
+  const int n_cand = ovl_launch_candidates(nullptr, 0);
+  if (ms && n_ms < n_cand) return w->fail(OVL_ERR_INVALID_ARG, "ms needs ovl_launch_candidates() entries");
+  int32_t sc[SC_COUNT];
+  if (!w->read_scal(sc)) return w->fail(OVL_ERR_DEVICE, "sync failed");
+  if (sc[SC_FLAGS]) {
+    ovl_status st = take_flags(w, sc[SC_FLAGS]);
+    if (st != OVL_OK) return st;
+  }
+  w->wp.forced = 0;
+  // contacts, graph, colours and rows of the step; grow once if a buffer overflowed
+  for (int attempt = 0;; ++attempt) {
+    hipError_t e = launch_collide(w->wp, w->scan_scratch, w->stream);
+    if (!e) e = launch_graph(w->wp, w->scan_scratch, w->stream);
+    if (!e) e = launch_solve_pre(w->wp, w->stream);
+    if (e) return w->fail(OVL_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    if (!w->read_scal(sc)) return w->fail(OVL_ERR_DEVICE, "step failed on the device");
+    if (!(sc[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP))) break;
+    if (attempt > 0 || !w->grow(sc)) return take_flags(w, sc[SC_FLAGS]);
+    w->write_scal(SC_FLAGS, 0);
+    w->write_scal(SC_PREV_NCOPY, 0);
+  }
+  if (sc[SC_FLAGS]) return take_flags(w, sc[SC_FLAGS]);
+  const ovl_launch_cfg keep = w->launch;
+  const int keep_k = w->wp.pgs_cfg;
+  hipEvent_t e0 = w->take_event(), e1 = w->take_event();
+  if (!e0 || !e1) return w->fail(OVL_ERR_DEVICE, "event creation failed");
+  std::vector<float> best_ms(n_cand, 0.0f);
+  unsigned long long ref_digest = 0;
+  int best = -1;
+  ovl_status result = OVL_OK;
+  for (int c = 0; c < n_cand && result == OVL_OK; ++c) {
+    const int k = c / 2;
+    const ovl_launch_cfg cand{kPgsCfgBlock[k], kPgsCfgReps[k], c % 2, keep.graph};
+    if (!w->apply_launch(cand, k)) {
+      result = w->fail(OVL_ERR_DEVICE, "occupancy query failed");
+      break;
+    }
+    float tmin = 0.0f;
+    for (int t = 0; t < trials; ++t) {
+      hipError_t e = launch_reset_lambda(w->wp, w->stream);
+      if (!e) e = hipEventRecord(e0, w->stream);
+      if (!e) e = launch_pgs(w->wp, w->stream);
+      if (!e) e = hipEventRecord(e1, w->stream);
+      if (!e) e = hipStreamSynchronize(w->stream);
+      float dt = 0.0f;
+      if (!e) e = hipEventElapsedTime(&dt, e0, e1);
+      if (e) {
+        result = w->fail(OVL_ERR_DEVICE, std::string("autotune launch failed: ") + hipGetErrorString(e));
+        break;
+      }
+      tmin = t == 0 ? dt : std::min(tmin, dt);
+    }
+    if (result != OVL_OK) break;
+    unsigned long long dg = 0;
+    if (launch_digest(w->wp, w->digest, w->stream) != hipSuccess ||
+        hipMemcpyAsync(&dg, w->digest, sizeof(dg), hipMemcpyDeviceToHost, w->stream) != hipSuccess ||
+        hipStreamSynchronize(w->stream) != hipSuccess) {
+      result = w->fail(OVL_ERR_DEVICE, "digest failed");
+      break;
+    }
+    if (c == 0) ref_digest = dg;
+    else if (dg != ref_digest) result = w->fail(OVL_ERR_DEVICE, "launch configurations gave different results");
+    best_ms[c] = tmin;
+    if (best < 0 || tmin < best_ms[best]) best = c;
+  }
+  w->ev_pool.push_back(e0);
+  w->ev_pool.push_back(e1);
+  if (result != OVL_OK) {
+    (void)w->apply_launch(keep, keep_k);
+    return result;
+  }
+  // finish the step with the fastest configuration
+  const int kb = best / 2;
+  const ovl_launch_cfg win{kPgsCfgBlock[kb], kPgsCfgReps[kb], best % 2, keep.graph};
+  (void)w->apply_launch(win, kb);
+  hipError_t e = launch_reset_lambda(w->wp, w->stream);
+  if (!e) e = launch_pgs(w->wp, w->stream);
+  if (!e) e = launch_solve_post(w->wp, w->stream, false);
+  if (e) return w->fail(OVL_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  if (!w->read_scal(sc)) return w->fail(OVL_ERR_DEVICE, "step failed on the device");
+  if (sc[SC_FLAGS]) return take_flags(w, sc[SC_FLAGS]);
+  if (chosen) *chosen = win;
+  if (ms)
+    for (int c = 0; c < n_cand; ++c) ms[c] = best_ms[c];
   return OVL_OK;
 }
 

@@ -115,3 +115,19 @@ def test_null_world_is_rejected():
     assert L.ovl_set_partitions(None, None, 0, None, 0, 1, 1) == ovl.ERR_INVALID_ARG
     assert L.ovl_read_state(None, None, 0, 0) == ovl.ERR_INVALID_ARG
     L.ovl_destroy_world(None)
+
+
+def test_launch_candidates_and_launch_validation():
+    L = ovl.lib()
+    cands = ovl.launch_candidates()
+    assert len(cands) == L.ovl_launch_candidates(None, 0) == 8
+    pairs = {(c["pgs_block"], c["pgs_lds_reps"]) for c in cands}
+    assert pairs == {(1024, 4800), (512, 2400), (256, 1200), (256, 2400)}
+    assert {c["persistent"] for c in cands} == {0, 1} and all(c["graph"] == 0 for c in cands)
+    # every LDS tile (two float4 per replica, plus the kernel's static LDS) fits the 160 KiB of a CU
+    for b, r in pairs:
+        assert 2 * r * 16 + 1024 <= 160 * 1024
+    cfg = ovl.ovl_launch_cfg(1024, 4800, 0, 0)
+    assert L.ovl_set_launch(None, C.byref(cfg)) == ovl.ERR_INVALID_ARG
+    assert L.ovl_get_launch(None, C.byref(cfg)) == ovl.ERR_INVALID_ARG
+    assert L.ovl_autotune(None, 1, None, None, 0) == ovl.ERR_INVALID_ARG
