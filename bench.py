@@ -160,7 +160,36 @@ def bench_batched(args):
                      [round(float(x), 4) for x in cand_ms]}
         log(f"[batched {name}] {res[name]['value']:.3e} body-steps/s, {res[name]['ms_per_step']:.3f} ms/step")
         w.close()
-    # a loop over one world per scene (default launch, no graph)
+    if args.skip_loop:
+        res["per_scene_loop"] = None
+    else:
+        res["per_scene_loop"] = per_scene_loop(sc, p, args, timed)
+    head = res["tuned"]
+    loop = res["per_scene_loop"]
+    out = {
+        "metric": "body-steps/s, batched scenes, 30 sweeps per step",
+        "value": head["value"], "unit": "body-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": (f"512 bowl scenes, spheres log-uniform 200..5000 per scene ({N} in all), r~U(0.2,0.5) m, "
+                         f"1..6 k-means partitions per scene ({int(sc.parts_per_scene.sum())} in all, fixed), "
+                         f"2-hop overlap, h 1/60 s, 30 sweeps per step, steps {args.warmup + 1}..."
+                         f"{args.warmup + steps} of the drop"),
+            "batched_tuned": res["tuned"], "batched_default": res["default"], "per_scene_loop": loop,
+            "speedup_vs_per_scene_loop": None if loop is None else loop["secs"] / head["secs"],
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+def per_scene_loop(sc, p, args, timed):
+    """One world per scene, stepped one after the other (default launch, no graph)."""
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    steps = args.steps or 50
+    N = sc.n_bodies
     parts = []
     off = np.searchsorted(sc.scene, np.arange(sc.n_scenes + 1))
     poff = np.concatenate([[0], np.cumsum(sc.parts_per_scene)])
@@ -186,28 +215,11 @@ def bench_batched(args):
             wsub.step(1)
 
     secs = timed(step_all, lambda: [wsub.sync() for wsub in parts])
-    res["per_scene_loop"] = {"secs": secs, "value": N * steps / secs, "ms_per_step": 1e3 * secs / steps}
-    log(f"[per-scene loop] {res['per_scene_loop']['value']:.3e} body-steps/s, "
-        f"{res['per_scene_loop']['ms_per_step']:.3f} ms/step")
+    r = {"secs": secs, "value": N * steps / secs, "ms_per_step": 1e3 * secs / steps}
+    log(f"[per-scene loop] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step")
     for wsub in parts:
         wsub.close()
-    head = res["tuned"]
-    out = {
-        "metric": "body-steps/s, batched scenes, 30 sweeps per step",
-        "value": head["value"], "unit": "body-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {
-            "workload": (f"512 bowl scenes, spheres log-uniform 200..5000 per scene ({N} in all), r~U(0.2,0.5) m, "
-                         f"1..6 k-means partitions per scene ({int(sc.parts_per_scene.sum())} in all, fixed), "
-                         f"2-hop overlap, h 1/60 s, 30 sweeps per step, steps {args.warmup + 1}..."
-                         f"{args.warmup + steps} of the drop"),
-            "batched_tuned": res["tuned"], "batched_default": res["default"],
-            "per_scene_loop": res["per_scene_loop"],
-            "speedup_vs_per_scene_loop": res["per_scene_loop"]["secs"] / head["secs"],
-        },
-    }
-    print(json.dumps(out), flush=True)
+    return r
 
 
 def main():
@@ -215,7 +227,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["tower", "bowl", "batched"], default="tower")
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 10; batched: 150, so the piles have formed)")
     ap.add_argument("--mode", choices=["adaptive", "fixed"], default="adaptive")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cap", type=int, default=1000)
@@ -224,6 +237,7 @@ def main():
     ap.add_argument("--warm", choices=["plain", "learned", "both"], default="both",
                     help="warm start of the timed run; 'both' times plain then learned and reports learned")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2403_17261_amd", "data", "warmstart_mlp.npz"))
+    ap.add_argument("--skip-loop", action="store_true", help="batched: leave out the per-scene loop")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -249,8 +263,12 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
         return
     if args.workload == "batched":
+        if args.warmup is None:
+            args.warmup = 150
         bench_batched(args)
         return
+    if args.warmup is None:
+        args.warmup = 10
     sc = scenes.config5(0) if args.workload == "tower" else scenes.config2(0)
     if args.steps is None:
         args.steps = sc.steps

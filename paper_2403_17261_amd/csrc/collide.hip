@@ -263,11 +263,20 @@ __device__ __forceinline__ void for_each_contact(const WP& w, int a, F&& f) {
   }
 }
 
+// Both passes walk the bodies in grid-bucket order (bbody), so the lanes of a
+// wavefront search neighbouring cells and share their cache lines.  The count
+// pass keeps the first kKeep keys of each body; the write pass copies them and
+// searches again only for bodies with more contacts.
 __global__ void k_contact_count(WP w) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= w.N) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= w.N) return;
+  const int a = w.bbody[i];
+  uint32_t* keep = w.c_keep + (int64_t)a * kKeep;
   int n = 0;
-  for_each_contact(w, a, [&](uint32_t) { ++n; });
+  for_each_contact(w, a, [&](uint32_t bkey) {
+    if (n < kKeep) keep[n] = bkey;
+    ++n;
+  });
   w.ccount[a] = n;
 }
 
@@ -349,18 +358,24 @@ __device__ void contact_geometry(const WP& w, int a, uint32_t bkey, float* g /*8
 }
 
 __global__ void k_contact_write(WP w) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= w.N) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= w.N) return;
+  const int a = w.bbody[i];
   const int o0 = w.coff[a];
   const int o1 = w.coff[a + 1];
   if (o1 > w.Ccap) {
     if (o0 < w.Ccap || a == 0) atomicOr(&w.scal[SC_FLAGS], F_CONTACT_CAP);
     return;
   }
-  int p = o0;
-  for_each_contact(w, a, [&](uint32_t bkey) {
-    if (p < o1) w.c_bkey[p++] = bkey;
-  });
+  if (o1 - o0 <= kKeep) {
+    const uint32_t* keep = w.c_keep + (int64_t)a * kKeep;
+    for (int k = 0; k < o1 - o0; ++k) w.c_bkey[o0 + k] = keep[k];
+  } else {
+    int p = o0;
+    for_each_contact(w, a, [&](uint32_t bkey) {
+      if (p < o1) w.c_bkey[p++] = bkey;
+    });
+  }
   // insertion sort of the body's short segment
   for (int i = o0 + 1; i < o1; ++i) {
     uint32_t k = w.c_bkey[i];

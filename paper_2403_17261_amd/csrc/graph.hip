@@ -333,13 +333,16 @@ __global__ void k_check_reps(WP w) {
   if (w.rep_off_bm[w.N] > w.Rcap) atomicOr(&w.scal[SC_FLAGS], F_REP_CAP);
 }
 
-__global__ void k_check_copies(WP w) {
-  if (threadIdx.x || blockIdx.x) return;
-  if (w.part_copy_off[w.G] > w.Mcap) atomicOr(&w.scal[SC_FLAGS], F_COPY_CAP);
+__global__ __launch_bounds__(1024) void k_check_copies(WP w) {
+  __shared__ int red[16];
   int nj = 0;
-  for (int g = 0; g < w.G; ++g) nj += w.mc_psize[1][g];
-  w.scal[SC_NJCOPY] = nj;
-  w.scal[SC_NCCOPY] = w.part_copy_off[w.G] - nj;
+  for (int g = threadIdx.x; g < w.G; g += 1024) nj += w.mc_psize[1][g];
+  nj = block_sum<1024>(nj, red);
+  if (threadIdx.x == 0) {
+    if (w.part_copy_off[w.G] > w.Mcap) atomicOr(&w.scal[SC_FLAGS], F_COPY_CAP);
+    w.scal[SC_NJCOPY] = nj;
+    w.scal[SC_NCCOPY] = w.part_copy_off[w.G] - nj;
+  }
 }
 
 __global__ void k_zero_scal(WP w) {
@@ -419,7 +422,7 @@ hipError_t launch_graph(const WP& w, int32_t* sc, hipStream_t s) {
   if ((e = mc_count<ContactItems>(w, w.Ccap, s, sc))) return e;
   if (w.G > 0) k_sum2<<<nblocks(w.G, kBlock), kBlock, 0, s>>>(w.mc_psize[1], w.mc_psize[2], w.g_tmp, w.G);
   if ((e = scan_excl(w.g_tmp, w.part_copy_off, w.G, &w.scal[SC_NCOPY], sc, s))) return e;
-  k_check_copies<<<1, 1, 0, s>>>(w);
+  k_check_copies<<<1, 1024, 0, s>>>(w);
   if ((e = mc_scatter<JointItems>(w, w.J, w.part_copy_off, nullptr, s))) return e;
   if ((e = mc_scatter<ContactItems>(w, w.Ccap, w.part_copy_off, w.mc_psize[1], s))) return e;
   return hipGetLastError();

@@ -17,6 +17,7 @@ constexpr int kPgsCfgCount = 4;
 constexpr int kPgsCfgBlock[kPgsCfgCount] = {1024, 512, 256, 256};
 constexpr int kPgsCfgReps[kPgsCfgCount] = {4800, 2400, 1200, 2400};
 constexpr int kBlock = 256;          // generic per-item kernels
+constexpr int kKeep = 16;            // contact keys per body kept between the two narrow-phase passes
 // warm-start network 12 -> 64 -> 64 -> 3
 constexpr int kMlpIn = 12, kMlpHid = 64, kMlpOut = 3;
 constexpr int kMlpParams = kMlpIn * kMlpHid + kMlpHid + kMlpHid * kMlpHid + kMlpHid + kMlpHid * kMlpOut + kMlpOut;
@@ -98,6 +99,7 @@ struct WP {
   int32_t* ccount;              // [N+1]
   int32_t* coff;                // [N+1]
   uint32_t* c_bkey;             // [Ccap] (bcode<<1)|sub
+  uint32_t* c_keep;             // [N*kKeep] contact keys found by the count pass
   int32_t* c_a;                 // [Ccap]
   float* c_geom;                // [8][Ccap]: n(3), phi, l_a, l_b, s_a, t_b: lever arms
                                 //   r_a = s_a u_a + l_a n, r_b = t_b u_b - l_b n (u: capsule axis)
@@ -140,10 +142,11 @@ struct WP {
   int32_t* part_col_off;        // [G*65]
   int32_t* part_ncol;           // [G]
   // rows (slot order = colour-sorted within each partition)
-  //   contact: rec0 = (n, a_duff), rec1 = (l_a, l_b, bias_n, mu), rec2 = (1/A_n, 1/A_t1, 1/A_t2, 0)
+  //   contact: rec0 = (n, a_duff), rec1 = (l_a, l_b, bias_n, mu), rec2 = (1/A_n, 1/A_t, A_n, A_t)
+  //            (a sphere contact has A_t1 = A_t2 = A_t)
   //   joint:   rec0 = (r_a, bias_x), rec1 = (r_b, bias_y), rec2 = (1/A_x, 1/A_y, 1/A_z, bias_z)
-  //   contact touching a capsule (kGenFlag): rec1 = (0, 0, bias_n, mu), and r_gen holds the
-  //   full lever arms (r_a, 0), (r_b, 0)
+  //   contact touching a capsule (kGenFlag): rec1 = (A_n, 0, bias_n, mu),
+  //   rec2 = (1/A_n, 1/A_t1, 1/A_t2, 0), and r_gen holds the full lever arms (r_a, A_t1), (r_b, A_t2)
   float4* r_rec;                // [3][Mcap]
   float4* r_gen;                // [2][Mcap] (only with capsules)
   int2* r_ids;                  // [Mcap] (local replica a | kJointFlag | kGenFlag, local replica b or -1)

@@ -417,7 +417,7 @@ __global__ void k_rows(WP w) {
       const float At = ima + imb + iia * la * la + iib * lb * lb + w.cfm;
       w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
       w.r_rec[MC + slot] = make_float4(la, lb, bias, mu);
-      w.r_rec[2 * MC + slot] = make_float4(1.0f / An, 1.0f / At, 1.0f / At, 0.0f);
+      w.r_rec[2 * MC + slot] = make_float4(1.0f / An, 1.0f / At, An, At);
       w.r_ids[slot] = make_int2(w.cp_ia[u], b >= 0 ? w.cp_ib[u] : -1);
     } else {
       // capsule contact: full lever arms, A_rr = m_a^-1 + m_b^-1 + sum (r x d).I^-1 (r x d)
@@ -433,10 +433,10 @@ __global__ void k_rows(WP w) {
         Ad[e] = ima + imb + dot(ca, inv_inertia(iia, ua, dIa, ca)) + dot(cb, inv_inertia(iib, ub, dIb, cb)) + w.cfm;
       }
       w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
-      w.r_rec[MC + slot] = make_float4(0.0f, 0.0f, bias, mu);
+      w.r_rec[MC + slot] = make_float4(Ad[0], 0.0f, bias, mu);
       w.r_rec[2 * MC + slot] = make_float4(1.0f / Ad[0], 1.0f / Ad[1], 1.0f / Ad[2], 0.0f);
-      w.r_gen[slot] = make_float4(ra.x, ra.y, ra.z, 0.0f);
-      w.r_gen[MC + slot] = make_float4(rb.x, rb.y, rb.z, 0.0f);
+      w.r_gen[slot] = make_float4(ra.x, ra.y, ra.z, Ad[1]);
+      w.r_gen[MC + slot] = make_float4(rb.x, rb.y, rb.z, Ad[2]);
       w.r_ids[slot] = make_int2(w.cp_ia[u] | kGenFlag, b >= 0 ? w.cp_ib[u] : -1);
     }
     if (warm) {
@@ -459,7 +459,13 @@ __global__ void k_rows(WP w) {
 
 // ---------------------------------------------------------- Gauss-Seidel ----
 // Replica velocity storage: two float4 per replica, (v, 1/m) and (w, 1/I), in
-// LDS, or for partitions too large for LDS in the partition's slice of rep_v4.
+// two arrays `stride` apart (so consecutive replicas are 16 B apart and random
+// gathers spread over all LDS banks): in LDS, or for partitions too large for
+// LDS in the partition's slice of rep_v4 (stride Rcap).
+struct Vel {
+  float4* p;
+  int stride;
+};
 
 struct Rec {
   float4 r0, r1, r2, lam;
@@ -492,14 +498,21 @@ struct Bod {
   float im, ii;
 };
 
-__device__ __forceinline__ Bod ld_body(const float4* V, int r) {
-  const float4 a = V[2 * r], b = V[2 * r + 1];
+__device__ __forceinline__ Bod ld_body(Vel V, int r) {
+  const float4 a = V.p[r], b = V.p[r + V.stride];
   return {mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), a.w, b.w};
 }
 
-__device__ __forceinline__ void st_body(float4* V, int r, const Bod& B) {
-  V[2 * r] = make_float4(B.v.x, B.v.y, B.v.z, B.im);
-  V[2 * r + 1] = make_float4(B.w.x, B.w.y, B.w.z, B.ii);
+// the inverse mass and inertia never change during the solve: only v and w are stored
+__device__ __forceinline__ void st_body(Vel V, int r, const Bod& B) {
+  float* a = reinterpret_cast<float*>(V.p + r);
+  float* b = reinterpret_cast<float*>(V.p + r + V.stride);
+  a[0] = B.v.x;
+  a[1] = B.v.y;
+  a[2] = B.v.z;
+  b[0] = B.w.x;
+  b[1] = B.w.y;
+  b[2] = B.w.z;
 }
 
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -525,7 +538,7 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
     const float nl = fmaxf(lam.x - wv * R.r2.x, 0.0f);
     dl = nl - lam.x;
     lam.x = nl;
-    rl = fmaxf(rl, fabsf(dl) * rcp_fast(R.r2.x));
+    rl = fmaxf(rl, fabsf(dl) * R.r2.z);
   } else {
     dl = lam.x;
   }
@@ -540,7 +553,7 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
     const float nl = fminf(fmaxf(lam.y - wv * R.r2.y, -hi), hi);
     dl = nl - lam.y;
     lam.y = nl;
-    rl = fmaxf(rl, fabsf(dl) * rcp_fast(R.r2.y));
+    rl = fmaxf(rl, fabsf(dl) * R.r2.w);
   } else {
     dl = lam.y;
   }
@@ -553,10 +566,10 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
     const f3 dv = sub(B.v, A.v);
     const f3 sw = add(scale(A.w, la), scale(B.w, lb));
     const float wv = dot(t2, dv) + dot(t1, sw) + cfm * lam.z;
-    const float nl = fminf(fmaxf(lam.z - wv * R.r2.z, -hi), hi);
+    const float nl = fminf(fmaxf(lam.z - wv * R.r2.y, -hi), hi);
     dl = nl - lam.z;
     lam.z = nl;
-    rl = fmaxf(rl, fabsf(dl) * rcp_fast(R.r2.z));
+    rl = fmaxf(rl, fabsf(dl) * R.r2.w);
   } else {
     dl = lam.z;
   }
@@ -619,6 +632,7 @@ __device__ __forceinline__ void gen_contact_rows(const Rec& R, Bod& A, Bod& B, f
   const float bias = R.r1.z, mu = R.r1.w;
   float* l = &lam.x;
   const float invd[3] = {R.r2.x, R.r2.y, R.r2.z};
+  const float Arr[3] = {R.r1.x, R.g0.w, R.g1.w};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const f3 d = k == 0 ? n : (k == 1 ? t1 : t2);
@@ -632,7 +646,7 @@ __device__ __forceinline__ void gen_contact_rows(const Rec& R, Bod& A, Bod& B, f
       const float nl = fminf(fmaxf(l[k] - wv * invd[k], lo), hi);
       dl = nl - l[k];
       l[k] = nl;
-      rl = fmaxf(rl, fabsf(dl) * rcp_fast(invd[k]));
+      rl = fmaxf(rl, fabsf(dl) * Arr[k]);
     } else {
       dl = l[k];
     }
@@ -644,7 +658,7 @@ __device__ __forceinline__ void gen_contact_rows(const Rec& R, Bod& A, Bod& B, f
 }
 
 template <bool solve, bool kCaps = false>
-__device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& rl, int slot, int r0 = 0) {
+__device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, int slot, int r0 = 0) {
   Bod A = ld_body(V, R.ia);
   Bod B;
   const bool hasB = R.ib >= 0;
@@ -671,13 +685,13 @@ __device__ __forceinline__ void do_slot(const WP& w, float4* V, Rec& R, float& r
 
 // replica velocities with gravity applied (v~ = v + h g) and inverse masses
 template <int BS>
-__device__ void load_replicas(const WP& w, float4* V, int r0, int nr) {
+__device__ void load_replicas(const WP& w, Vel V, int r0, int nr) {
   const int N = w.N;
   const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
   for (int r = threadIdx.x; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
-    V[2 * r] = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
-    V[2 * r + 1] = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
+    V.p[r] = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
+    V.p[r + V.stride] = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
   }
 }
 
@@ -721,7 +735,8 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
     hi[1] = hi[2] = R.r1.w * l[0];
     lo[1] = lo[2] = -hi[1];
   }
-  const float invd[3] = {R.r2.x, R.r2.y, R.r2.z};
+  // sphere contacts keep one 1/A for both tangents (the record's z, w hold A_n, A_t)
+  const float invd[3] = {R.r2.x, R.r2.y, (R.joint || R.gen) ? R.r2.z : R.r2.y};
   float e = 0.0f;
   for (int k = 0; k < 3; ++k) {
     const float wv = vr[k] + bias[k] + cfm * l[k];
@@ -735,7 +750,7 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
 // solve order, take the largest natural-map residual of the partition's rows,
 // then restore v~.  Uniform over the workgroup.
 template <int BS, bool kCaps>
-__device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const int* coff, int r0, int nr,
+__device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int* coff, int r0, int nr,
                                 bool learned, float* red) {
   const int tid = threadIdx.x;
   float unused = 0.0f;
@@ -768,7 +783,7 @@ __device__ float start_residual(const WP& w, float4* V, int s0, int ncol, const 
 // Solve one partition with a workgroup of BS threads.  V holds its replica
 // velocities (LDS, or its slice of rep_v4 for the global variant).
 template <int BS, bool kCaps>
-__device__ void solve_partition(const WP& w, int p, float4* V, int* coff, float* red) {
+__device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red) {
   const int tid = threadIdx.x;
   const int N = w.N;
   const int r0 = w.part_rep_off[p];
@@ -903,7 +918,7 @@ __global__ __launch_bounds__(BS) void k_pgs(WP w) {
     const int p = w.part_order[k];
     const int nr = w.part_rep_off[p + 1] - w.part_rep_off[p];
     if (kLds == (nr <= kReps)) {  // otherwise the other variant handles this partition
-      float4* V = kLds ? sm4 : w.rep_v4 + 2 * (int64_t)w.part_rep_off[p];
+      const Vel V = kLds ? Vel{sm4, kReps} : Vel{w.rep_v4 + w.part_rep_off[p], w.Rcap};
       solve_partition<BS, kCaps>(w, p, V, coff, red);
     }
     if (!w.pgs_persistent) break;
@@ -911,21 +926,23 @@ __global__ __launch_bounds__(BS) void k_pgs(WP w) {
 }
 
 // Partitions in descending order of constraint copies (ties: ascending id),
-// by counting ranks in one workgroup; more than kOrderMax partitions keep
-// their natural order.
-constexpr int kOrderBS = 1024;
+// by counting ranks: every workgroup reads all keys into LDS and ranks its
+// slice of the partitions.  More than kOrderMax partitions keep their
+// natural order.
+constexpr int kOrderBS = 256;
 constexpr int kOrderMax = 8192;
 
 __global__ __launch_bounds__(kOrderBS) void k_part_order(WP w) {
   __shared__ int key[kOrderMax];
   const int G = w.G;
+  const int p = blockIdx.x * kOrderBS + threadIdx.x;
   if (G > kOrderMax) {
-    for (int p = threadIdx.x; p < G; p += kOrderBS) w.part_order[p] = p;
+    if (p < G) w.part_order[p] = p;
     return;
   }
-  for (int p = threadIdx.x; p < G; p += kOrderBS) key[p] = w.part_copy_off[p + 1] - w.part_copy_off[p];
+  for (int q = threadIdx.x; q < G; q += kOrderBS) key[q] = w.part_copy_off[q + 1] - w.part_copy_off[q];
   __syncthreads();
-  for (int p = threadIdx.x; p < G; p += kOrderBS) {
+  if (p < G) {
     const int kp = key[p];
     int rank = 0;
     for (int q = 0; q < G; ++q) {
@@ -1037,14 +1054,19 @@ __global__ void k_cache(WP w) {
   }
 }
 
-__global__ void k_commit(WP w) {
-  if (threadIdx.x || blockIdx.x) return;
-  if (w.scal[SC_FLAGS] != 0) return;
-  w.scal[SC_PREV_NCOPY] = w.part_copy_off[w.G];
-  w.scal[SC_COMMITTED] += 1;
-  int mx = 0, unconv = 0;
-  int64_t bytes = 0, sweeps = 0;
-  for (int g = 0; g < w.G; ++g) {
+// Commit of a step (one workgroup): the warm-start cache becomes this step's,
+// and the per-partition sweep counts are summed into the counters.
+constexpr int kCommitBS = 1024;
+
+__global__ __launch_bounds__(kCommitBS) void k_commit(WP w) {
+  __shared__ int failed_s;
+  __shared__ long long part[4][kCommitBS / 64];
+  if (threadIdx.x == 0) failed_s = w.scal[SC_FLAGS] != 0;
+  __syncthreads();
+  if (failed_s) return;
+  int mx = 0;
+  long long unconv = 0, bytes = 0, sweeps = 0;
+  for (int g = threadIdx.x; g < w.G; g += kCommitBS) {
     const int it = w.part_iters[g];
     mx = max(mx, it);
     if (w.adaptive && !w.forced && it >= w.max_iters && w.part_resid[g] > w.tol) ++unconv;
@@ -1052,11 +1074,31 @@ __global__ void k_commit(WP w) {
     bytes += (int64_t)it * ((nc - ns) * kBytesDynDyn + ns * kBytesStatic + nj * kBytesJoint);
     sweeps += it;
   }
-  w.stat_i64[0] += mx;
-  w.stat_i64[1] += unconv;
-  w.stat_i64[2] += bytes;
-  w.stat_i64[3] += sweeps;
-  w.stat_i64[4] += 1;
+  long long v[4] = {mx, unconv, bytes, sweeps};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const long long o = __shfl_xor(v[k], d, 64);
+      v[k] = k == 0 ? max(v[k], o) : v[k] + o;
+    }
+  if (lane_id() == 0)
+    for (int k = 0; k < 4; ++k) part[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t[4] = {0, 0, 0, 0};
+    for (int i = 0; i < kCommitBS / 64; ++i) {
+      t[0] = max(t[0], part[0][i]);
+      for (int k = 1; k < 4; ++k) t[k] += part[k][i];
+    }
+    w.scal[SC_PREV_NCOPY] = w.part_copy_off[w.G];
+    w.scal[SC_COMMITTED] += 1;
+    w.stat_i64[0] += t[0];
+    w.stat_i64[1] += t[1];
+    w.stat_i64[2] += t[2];
+    w.stat_i64[3] += t[3];
+    w.stat_i64[4] += 1;
+  }
 }
 
 // natural-map residual of the final iterate, one workgroup per partition: for
@@ -1128,7 +1170,7 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
     }
     invd[0] = R.r2.x;
     invd[1] = R.r2.y;
-    invd[2] = R.r2.z;
+    invd[2] = (R.joint || R.gen) ? R.r2.z : R.r2.y;
     for (int k = 0; k < 3; ++k) {
       const float wv = vr[k] + bias[k] + w.cfm * l[k];
       const float pr = fminf(fmaxf(l[k] - wv * invd[k], lo[k]), hi[k]);
@@ -1207,7 +1249,7 @@ hipError_t pgs_occupancy(int cfg, bool caps, int* per_cu_lds, int* per_cu_glob) 
 hipError_t launch_solve_pre(const WP& w, hipStream_t s) {
   hipError_t e;
   if (w.G > 0) {
-    k_part_order<<<1, kOrderBS, 0, s>>>(w);
+    k_part_order<<<nblocks(w.G, kOrderBS), kOrderBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
     k_colour<<<w.G, kColBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
@@ -1257,7 +1299,7 @@ hipError_t launch_solve_post(const WP& w, hipStream_t s, bool exact_residual) {
     k_cache<<<nblocks(w.Mcap, kBlock), kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
-  k_commit<<<1, 1, 0, s>>>(w);
+  k_commit<<<1, kCommitBS, 0, s>>>(w);
   return hipGetLastError();
 }
 
