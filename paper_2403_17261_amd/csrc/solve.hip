@@ -824,19 +824,28 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   const int cap = w.forced ? w.part_force_iters[p] : w.max_iters;
   int it = 0;
   float rho = 0.0f;
+  // With a single colour the next record would be the current one, read before
+  // its impulses are stored: then nothing is prefetched and every slot is
+  // loaded where it is solved.
+  const int first = ncol == 1 ? 0 : BS;
+  // colour offsets in two registers (lane k holds coff[k]); read with readlane
+  const int cv0 = coff[lane_id()];
+  const int cv1 = coff[kColStride - 1];
+  auto co = [&](int k) { return k < 64 ? __builtin_amdgcn_readlane(cv0, k) : cv1; };
   Rec cur;
-  bool has_cur = ncol > 0 && coff[0] + tid < coff[1];
-  if (has_cur) load_rec<kCaps>(w, s0 + coff[0] + tid, cur);
+  bool has_cur = ncol > 1 && co(0) + tid < co(1);
+  if (has_cur) load_rec<kCaps>(w, s0 + co(0) + tid, cur);
   while (it < cap) {
     rl = 0.0f;
     for (int c = 0; c < ncol; ++c) {
       const int cn = c + 1 < ncol ? c + 1 : 0;
+      const int b0 = co(c), b1 = co(c + 1), n0 = co(cn), n1 = co(cn + 1);
       Rec nxt;
-      const bool has_nxt = coff[cn] + tid < coff[cn + 1];
-      if (has_nxt) load_rec<kCaps>(w, s0 + coff[cn] + tid, nxt);
-      if (has_cur) do_slot<true, kCaps>(w, V, cur, rl, s0 + coff[c] + tid, r0);
-      const int e = s0 + coff[c + 1];
-      for (int slot = s0 + coff[c] + tid + BS; slot < e; slot += BS) {
+      const bool has_nxt = ncol > 1 && n0 + tid < n1;
+      if (has_nxt) load_rec<kCaps>(w, s0 + n0 + tid, nxt);
+      if (has_cur) do_slot<true, kCaps>(w, V, cur, rl, s0 + b0 + tid, r0);
+      const int e = s0 + b1;
+      for (int slot = s0 + b0 + tid + first; slot < e; slot += BS) {
         Rec R;
         load_rec<kCaps>(w, slot, R);
         do_slot<true, kCaps>(w, V, R, rl, slot, r0);

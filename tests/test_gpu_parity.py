@@ -193,3 +193,21 @@ def test_full_size_sampled(which):
         w, p = make_world(sc)
         w.step(100)
         compare_step(sc, w, p, label="chains51k t=100")
+
+
+def test_single_colour_partition_keeps_its_impulses():
+    """Spheres resting apart on the ground: every contact is independent, so a
+    partition has one colour and each sweep revisits the same records.  The
+    impulses after the solve must be the converged ones (m g h each, cold start)."""
+    n = 12
+    pos = [[1.5 * i, 0.0, 0.5] for i in range(n)]
+    sc = scenes.custom_spheres(pos, 0.5, 1.0 + np.arange(n) * 0.25, planes=scenes.GROUND, iters=20)
+    w, p = make_world(sc, warmstart=ovl.WARM_NONE)
+    w.step(1)
+    lam = w.debug("copy_lambda")
+    colours = w.debug("copy_colour")
+    o = oracle.step(sc, warmstart=False, max_iters=20)
+    log(f"  colours {sorted(set(colours.tolist()))}, lambda_n {lam[:4, 0].tolist()} oracle {o['copy_lambda'][:4, 0].tolist()}")
+    assert set(colours.tolist()) == {0}
+    assert np.abs(lam - o["copy_lambda"]).max() <= 1e-6 * np.abs(o["copy_lambda"]).max()
+    assert lam[:, 0] == pytest.approx(sc.mass * 9.81 / 60.0, rel=1e-5)
