@@ -158,6 +158,17 @@ ovl_status ovl_set_partitions(ovl_world* w, const int32_t* owner, int64_t n_bodi
  * NOT_CONVERGED is informational (the state advanced). */
 ovl_status ovl_step(ovl_world* w, int32_t n_steps, ovl_step_stats* stats, int32_t compute_exact_residual);
 
+/* Replace the warm-start cache (checkpoint restore of the impulses the next
+ * step starts from; plain warm start, reading R16).  n entries, strictly
+ * increasing in (part, kind, key), as ovl_read_debug exports them
+ * (CACHE_PART, CACHE_KIND, CACHE_KEY, CACHE_VAL): part a global partition id,
+ * kind 0 joint (key = joint index, val = its three impulses, 0) or 1 contact
+ * (key = (a<<32)|(bcode<<1)|sub, val = lambda_n and the friction impulse as a
+ * world vector).  Host arrays, copied.  INVALID_ARG (unsorted, bad partition
+ * or kind, non-finite value), CAPACITY (n above the copy capacity), DEVICE. */
+ovl_status ovl_write_cache(ovl_world* w, const int32_t* part, const int32_t* kind, const uint64_t* key,
+                           const float* val, int64_t n);
+
 /* Copy the blended states, [n_bodies][13] float32, into dst (host, or device
  * when dst_is_device != 0).  Synchronises the stream.  Errors: INVALID_ARG
  * (n_bodies differs), a pending CAPACITY/NONFINITE error, DEVICE. */

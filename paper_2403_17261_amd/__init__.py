@@ -108,6 +108,7 @@ def lib():
             "ovl_step": (C.c_int, [P, C.c_int32, C.POINTER(ovl_step_stats), C.c_int32]),
             "ovl_read_state": (C.c_int, [P, P, C.c_int64, C.c_int32]),
             "ovl_write_state": (C.c_int, [P, P, C.c_int64, C.c_int32, C.c_int32]),
+            "ovl_write_cache": (C.c_int, [P, P, P, P, P, C.c_int64]),
             "ovl_synchronize": (C.c_int, [P]),
             "ovl_read_debug": (C.c_int, [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]),
             "ovl_force_iters": (C.c_int, [P, P, C.c_int32]),
@@ -358,6 +359,14 @@ class World:
 
     def cache(self):
         return {k: self.debug(k) for k in ("cache_part", "cache_kind", "cache_key", "cache_val")}
+
+    def write_cache(self, cache):
+        """Restore a warm-start cache exported by cache()."""
+        part = np.ascontiguousarray(cache["cache_part"], np.int32)
+        kind = np.ascontiguousarray(cache["cache_kind"], np.int32)
+        key = np.ascontiguousarray(cache["cache_key"], np.uint64)
+        val = np.ascontiguousarray(cache["cache_val"], np.float32).reshape(-1, 4)
+        self._check(lib().ovl_write_cache(self.h, _p(part), _p(kind), _p(key), _p(val), len(part)))
 
     def set_launch(self, pgs_block=1024, pgs_lds_reps=4800, persistent=0, graph=0):
         c = ovl_launch_cfg(int(pgs_block), int(pgs_lds_reps), int(persistent), int(graph))

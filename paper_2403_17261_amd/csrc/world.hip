@@ -1040,6 +1040,34 @@ ovl_status ovl_write_state(ovl_world* w, const float* src, int64_t n_bodies, int
   return OVL_OK;
 }
 
+ovl_status ovl_write_cache(ovl_world* w, const int32_t* part, const int32_t* kind, const uint64_t* key,
+                           const float* val, int64_t n) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!part || !kind || !key || !val))) return w->fail(OVL_ERR_INVALID_ARG, "bad cache arrays");
+  if (n > w->wp.Mcap) return w->fail(OVL_ERR_CAPACITY, "cache larger than the copy capacity");
+  for (int64_t i = 0; i < n; ++i) {
+    if (part[i] < 0 || part[i] >= w->G || (kind[i] != 0 && kind[i] != 1))
+      return w->fail(OVL_ERR_INVALID_ARG, "cache entry with a bad partition or kind");
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(val[4 * i + k])) return w->fail(OVL_ERR_INVALID_ARG, "non-finite cached impulse");
+    if (i > 0) {
+      const bool less = part[i - 1] < part[i] ||
+                        (part[i - 1] == part[i] && (kind[i - 1] < kind[i] || (kind[i - 1] == kind[i] && key[i - 1] < key[i])));
+      if (!less) return w->fail(OVL_ERR_INVALID_ARG, "cache entries must be strictly increasing in (part, kind, key)");
+    }
+  }
+  const int64_t MC = w->wp.Mcap;
+  std::vector<float> cols((size_t)4 * MC, 0.0f);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 4; ++k) cols[(size_t)k * MC + i] = val[4 * i + k];
+  if (hipStreamSynchronize(w->stream) != hipSuccess || !w->upload(w->wp.wc_part, part, n * sizeof(int32_t)) ||
+      !w->upload(w->wp.wc_kind, kind, n * sizeof(int32_t)) || !w->upload(w->wp.wc_key, key, n * sizeof(uint64_t)) ||
+      !w->upload(w->wp.wc_val, cols.data(), cols.size() * sizeof(float)) || hipStreamSynchronize(w->stream) != hipSuccess)
+    return w->fail(OVL_ERR_DEVICE, "upload failed");
+  w->write_scal(SC_PREV_NCOPY, (int32_t)n);
+  return OVL_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ debug ----

@@ -211,3 +211,28 @@ def test_single_colour_partition_keeps_its_impulses():
     assert set(colours.tolist()) == {0}
     assert np.abs(lam - o["copy_lambda"]).max() <= 1e-6 * np.abs(o["copy_lambda"]).max()
     assert lam[:, 0] == pytest.approx(sc.mass * 9.81 / 60.0, rel=1e-5)
+
+
+def test_checkpoint_with_warm_start_cache_is_bitwise():
+    """State plus warm-start cache restore a run exactly, in a fresh world."""
+    sc = scenes.config5(5, nx=8, ny=8, nz=5, cols=2)
+    w, p = make_world(sc)
+    w.step(20)
+    ckpt, cache = w.read_state(), w.cache()
+    assert len(cache["cache_part"]) > 100
+    w.step(10)
+    a = w.read_state()
+    w2, _ = make_world(sc)
+    w2.write_state(ckpt)
+    w2.write_cache(cache)
+    w2.step(10)
+    assert np.array_equal(a, w2.read_state())
+    # an unsorted cache is rejected
+    bad = {k: v.copy() for k, v in cache.items()}
+    bad["cache_key"][[0, 1]] = bad["cache_key"][[1, 0]]
+    bad["cache_part"][[0, 1]] = bad["cache_part"][[1, 0]]
+    bad["cache_kind"][[0, 1]] = bad["cache_kind"][[1, 0]]
+    if (bad["cache_part"][0], bad["cache_kind"][0], bad["cache_key"][0]) > \
+            (bad["cache_part"][1], bad["cache_kind"][1], bad["cache_key"][1]):
+        with pytest.raises(ovl.OvlError):
+            w2.write_cache(bad)
