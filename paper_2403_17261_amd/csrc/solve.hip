@@ -111,6 +111,7 @@ __device__ __forceinline__ bool prio_gt(uint32_t ha, int ua, uint32_t hb, int ub
 
 constexpr int kColBS = 1024;
 constexpr int kColWaves = kColBS / 64;
+constexpr int kColLds = 24576;  // partitions with at most this many copies keep their colours in LDS
 
 __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   __shared__ int lds_i[kColWaves];
@@ -119,6 +120,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   __shared__ int running[kMaxColours];
   __shared__ int wcnt[kColWaves][kMaxColours];
   __shared__ int any_s;
+  __shared__ signed char col_lds[kColLds];
   const int p = w.part_order[blockIdx.x];  // largest partitions first
   const int tid = threadIdx.x;
   if (tid == 0) any_s = (w.scal[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP)) ? 1 : 0;
@@ -132,11 +134,15 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   // incidence lists of the partition's replicas
   for (int r = tid; r < nr; r += kColBS) inc_cnt[r0 + r] = 0;
   __syncthreads();
+  const bool in_lds = u1 - u0 <= kColLds;  // uniform over the workgroup
   for (int u = u0 + tid; u < u1; u += kColBS) {
     atomicAdd(&inc_cnt[r0 + w.cp_ia[u]], 1);
     int ib = w.cp_ib[u];
     if (ib >= 0) atomicAdd(&inc_cnt[r0 + ib], 1);
-    w.cp_colour[u] = -1;
+    if (in_lds)
+      col_lds[u - u0] = -1;
+    else
+      w.cp_colour[u] = -1;
   }
   __syncthreads();
   {
@@ -161,12 +167,18 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
     if (ib >= 0) w.inc[w.inc_off[r0 + ib] + atomicAdd(&inc_cnt[r0 + ib], 1)] = u;
   }
   __syncthreads();
-  // Jones-Plassmann rounds
+  // Jones-Plassmann rounds.  A neighbour seen uncoloured may be coloured by
+  // another thread in the same round; either way the outcome is the same
+  // (a copy waits only for higher-priority ones, whose colours are final).
+  auto colour_of = [&](int o) -> int {
+    return in_lds ? (int)col_lds[o - u0]
+                  : __hip_atomic_load(&w.cp_colour[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
   bool overflow = false;
   for (;;) {
     bool pending = false;
     for (int u = u0 + tid; u < u1; u += kColBS) {
-      if (__hip_atomic_load(&w.cp_colour[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= 0) continue;
+      if (colour_of(u) >= 0) continue;
       const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
       uint64_t used = 0;
       bool ready = true;
@@ -177,7 +189,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
         for (int k = k0; k < k1; ++k) {
           int o = w.inc[k];
           if (o == u) continue;
-          int co = __hip_atomic_load(&w.cp_colour[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          int co = colour_of(o);
           if (co >= 0) {
             used |= 1ull << co;
           } else if (prio_gt(fmix32((uint32_t)o ^ w.seed), o, hu, u)) {
@@ -194,7 +206,10 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
         } else {
           c = __ffsll((unsigned long long)~used) - 1;
         }
-        __hip_atomic_store(&w.cp_colour[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (in_lds)
+          col_lds[u - u0] = (signed char)c;
+        else
+          __hip_atomic_store(&w.cp_colour[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       } else {
         pending = true;
       }
@@ -202,6 +217,9 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
     if (!__syncthreads_or(pending)) break;
   }
   if (__syncthreads_or(overflow) && tid == 0) atomicOr(&w.scal[SC_FLAGS], F_COLOUR_CAP);
+  if (in_lds)
+    for (int u = u0 + tid; u < u1; u += kColBS) w.cp_colour[u] = col_lds[u - u0];
+  __syncthreads();
   // colour histogram and offsets
   if (tid < kMaxColours) {
     ccount[tid] = 0;
@@ -469,28 +487,41 @@ struct Vel {
 
 struct Rec {
   float4 r0, r1, r2, lam;
-  float4 g0, g1;  // capsule rows only: (r_a, 0), (r_b, 0)
+  float4 g0, g1;  // capsule rows only: (r_a, A_t1), (r_b, A_t2)
+  int2 id;        // raw ids as stored
   int ia, ib;
   bool joint, gen;
 };
 
-// kCaps: the world has capsules, so a record may carry kGenFlag and full lever arms
+// Issue the loads of a record without using them, so a prefetch does not wait
+// for its data (decode() reads the ids when the record is solved).  kCaps: the
+// world has capsules; the lever-arm records are then always loaded.
 template <bool kCaps>
-__device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R) {
+__device__ __forceinline__ void fetch_rec(const WP& w, int slot, Rec& R) {
   const int64_t MC = w.Mcap;
   R.r0 = w.r_rec[slot];
   R.r1 = w.r_rec[MC + slot];
   R.r2 = w.r_rec[2 * MC + slot];
-  const int2 id = w.r_ids[slot];
-  R.joint = (id.x & kJointFlag) != 0;
-  R.gen = kCaps && (id.x & kGenFlag) != 0;
-  R.ia = id.x & ~(kJointFlag | kGenFlag);
-  R.ib = id.y;
+  R.id = w.r_ids[slot];
   R.lam = w.r_lam[slot];
-  if (kCaps && R.gen && !R.joint) {
+  if (kCaps) {
     R.g0 = w.r_gen[slot];
     R.g1 = w.r_gen[MC + slot];
   }
+}
+
+template <bool kCaps>
+__device__ __forceinline__ void decode(Rec& R) {
+  R.joint = (R.id.x & kJointFlag) != 0;
+  R.gen = kCaps && (R.id.x & kGenFlag) != 0;
+  R.ia = R.id.x & ~(kJointFlag | kGenFlag);
+  R.ib = R.id.y;
+}
+
+template <bool kCaps>
+__device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R) {
+  fetch_rec<kCaps>(w, slot, R);
+  decode<kCaps>(R);
 }
 
 struct Bod {
@@ -659,6 +690,7 @@ __device__ __forceinline__ void gen_contact_rows(const Rec& R, Bod& A, Bod& B, f
 
 template <bool solve, bool kCaps = false>
 __device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, int slot, int r0 = 0) {
+  decode<kCaps>(R);
   Bod A = ld_body(V, R.ia);
   Bod B;
   const bool hasB = R.ib >= 0;
@@ -834,7 +866,11 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   auto co = [&](int k) { return k < 64 ? __builtin_amdgcn_readlane(cv0, k) : cv1; };
   Rec cur;
   bool has_cur = ncol > 1 && co(0) + tid < co(1);
-  if (has_cur) load_rec<kCaps>(w, s0 + co(0) + tid, cur);
+  if (has_cur) fetch_rec<kCaps>(w, s0 + co(0) + tid, cur);
+  // Nothing may still be in flight into `cur` when the loop is entered:
+  // otherwise the wait placed before its first use would also hold back the
+  // next colour's prefetch in every iteration.
+  __builtin_amdgcn_s_waitcnt(0);
   while (it < cap) {
     rl = 0.0f;
     for (int c = 0; c < ncol; ++c) {
@@ -842,7 +878,7 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
       const int b0 = co(c), b1 = co(c + 1), n0 = co(cn), n1 = co(cn + 1);
       Rec nxt;
       const bool has_nxt = ncol > 1 && n0 + tid < n1;
-      if (has_nxt) load_rec<kCaps>(w, s0 + n0 + tid, nxt);
+      if (has_nxt) fetch_rec<kCaps>(w, s0 + n0 + tid, nxt);
       if (has_cur) do_slot<true, kCaps>(w, V, cur, rl, s0 + b0 + tid, r0);
       const int e = s0 + b1;
       for (int slot = s0 + b0 + tid + first; slot < e; slot += BS) {
@@ -1126,8 +1162,10 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
   float e = 0.0f;
   for (int slot = s0 + threadIdx.x; slot < s1; slot += 256) {
     Rec R;
-    load_rec<true>(w, slot, R);
-    if (!w.has_caps) R.gen = false;
+    if (w.has_caps)
+      load_rec<true>(w, slot, R);
+    else
+      load_rec<false>(w, slot, R);
     Bod A, B;
     const int ra_ = r0 + R.ia;
     A.v = mk(w.rst[7 * RC + ra_], w.rst[8 * RC + ra_], w.rst[9 * RC + ra_]);
