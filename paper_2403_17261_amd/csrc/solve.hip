@@ -111,7 +111,7 @@ __device__ __forceinline__ bool prio_gt(uint32_t ha, int ua, uint32_t hb, int ub
 
 constexpr int kColBS = 1024;
 constexpr int kColWaves = kColBS / 64;
-constexpr int kColLds = 24576;  // partitions with at most this many copies keep their colours in LDS
+constexpr int kColLds = 16384;  // partitions with at most this many copies colour in LDS (3 B per copy)
 
 __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   __shared__ int lds_i[kColWaves];
@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   __shared__ int wcnt[kColWaves][kMaxColours];
   __shared__ int any_s;
   __shared__ signed char col_lds[kColLds];
+  __shared__ uint32_t wait_lds[kColLds / 2];  // two 16-bit counters per word
   const int p = w.part_order[blockIdx.x];  // largest partitions first
   const int tid = threadIdx.x;
   if (tid == 0) any_s = (w.scal[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP)) ? 1 : 0;
@@ -134,16 +135,25 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   // incidence lists of the partition's replicas
   for (int r = tid; r < nr; r += kColBS) inc_cnt[r0 + r] = 0;
   __syncthreads();
-  const bool in_lds = u1 - u0 <= kColLds;  // uniform over the workgroup
   for (int u = u0 + tid; u < u1; u += kColBS) {
     atomicAdd(&inc_cnt[r0 + w.cp_ia[u]], 1);
     int ib = w.cp_ib[u];
     if (ib >= 0) atomicAdd(&inc_cnt[r0 + ib], 1);
+  }
+  __syncthreads();
+  // The LDS path keeps 16-bit wait counters: every replica must touch fewer
+  // than 2^14 copies so that a copy's count stays below 2^15.  Uniform.
+  bool busy = false;
+  for (int r = tid; r < nr; r += kColBS) busy |= inc_cnt[r0 + r] >= (1 << 14);
+  const bool in_lds = u1 - u0 <= kColLds && !__syncthreads_or(busy);
+  for (int u = u0 + tid; u < u1; u += kColBS) {
     if (in_lds)
       col_lds[u - u0] = -1;
     else
       w.cp_colour[u] = -1;
   }
+  if (in_lds)
+    for (int i = tid; i < (u1 - u0 + 1) / 2; i += kColBS) wait_lds[i] = 0;
   __syncthreads();
   {
     int carry = 2 * u0;
@@ -167,58 +177,122 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
     if (ib >= 0) w.inc[w.inc_off[r0 + ib] + atomicAdd(&inc_cnt[r0 + ib], 1)] = u;
   }
   __syncthreads();
-  // Jones-Plassmann rounds.  A neighbour seen uncoloured may be coloured by
-  // another thread in the same round; either way the outcome is the same
-  // (a copy waits only for higher-priority ones, whose colours are final).
-  auto colour_of = [&](int o) -> int {
-    return in_lds ? (int)col_lds[o - u0]
-                  : __hip_atomic_load(&w.cp_colour[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  };
+  // Jones-Plassmann.  In LDS (the common case): every copy counts its
+  // conflicting copies of higher priority; each round colours the copies whose
+  // count is zero (an independent set: of two conflicting copies the lower one
+  // still counts the higher), then those copies release their lower-priority
+  // neighbours.  Every neighbour list is read twice in all, not once per round.
+  // Otherwise (larger partitions) the same rounds run on global colours, each
+  // round rechecking the uncoloured copies.
   bool overflow = false;
-  for (;;) {
-    bool pending = false;
-    for (int u = u0 + tid; u < u1; u += kColBS) {
-      if (colour_of(u) >= 0) continue;
+  auto pick = [&](uint64_t used) -> int {
+    if (used == ~0ull) {
+      overflow = true;
+      return kMaxColours - 1;
+    }
+    return __ffsll((unsigned long long)~used) - 1;
+  };
+  if (in_lds) {
+    const int per = (u1 - u0 + kColBS - 1) / kColBS;  // copies per thread, at most 16
+    uint32_t todo = 0;
+    for (int j = 0; j < per; ++j) {
+      const int u = u0 + tid + j * kColBS;
+      if (u >= u1) break;
+      todo |= 1u << j;
       const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
-      uint64_t used = 0;
-      bool ready = true;
-      int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
-      for (int e = 0; e < 2 && ready; ++e) {
+      int n = 0;
+      const int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
+      for (int e = 0; e < 2; ++e) {
         if (ends[e] < 0) continue;
         const int k0 = w.inc_off[ends[e]], k1 = k0 + inc_cnt[ends[e]];
         for (int k = k0; k < k1; ++k) {
-          int o = w.inc[k];
-          if (o == u) continue;
-          int co = colour_of(o);
-          if (co >= 0) {
-            used |= 1ull << co;
-          } else if (prio_gt(fmix32((uint32_t)o ^ w.seed), o, hu, u)) {
-            ready = false;
-            break;
+          const int o = w.inc[k];
+          if (o != u && prio_gt(fmix32((uint32_t)o ^ w.seed), o, hu, u)) ++n;
+        }
+      }
+      atomicAdd(&wait_lds[(u - u0) >> 1], (uint32_t)n << (16 * ((u - u0) & 1)));
+    }
+    __syncthreads();
+    // each round colours at least the highest-priority uncoloured copy, so at
+    // most u1 - u0 rounds run; the bound only guards against a broken count
+    for (int round = 0;; ++round) {
+      if (round > u1 - u0) {
+        overflow = true;
+        break;
+      }
+      uint32_t now = 0;
+      for (uint32_t t = todo; t; t &= t - 1) {
+        const int j = __ffs(t) - 1;
+        const int u = u0 + tid + j * kColBS;
+        const uint32_t wv = wait_lds[(u - u0) >> 1] >> (16 * ((u - u0) & 1));
+        if ((wv & 0xffffu) != 0) continue;
+        uint64_t used = 0;
+        const int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
+        for (int e = 0; e < 2; ++e) {
+          if (ends[e] < 0) continue;
+          const int k0 = w.inc_off[ends[e]], k1 = k0 + inc_cnt[ends[e]];
+          for (int k = k0; k < k1; ++k) {
+            const int co = col_lds[w.inc[k] - u0];
+            if (co >= 0) used |= 1ull << co;
+          }
+        }
+        col_lds[u - u0] = (signed char)pick(used);
+        now |= 1u << j;
+      }
+      todo &= ~now;
+      __syncthreads();
+      for (uint32_t t = now; t; t &= t - 1) {
+        const int j = __ffs(t) - 1;
+        const int u = u0 + tid + j * kColBS;
+        const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
+        const int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
+        for (int e = 0; e < 2; ++e) {
+          if (ends[e] < 0) continue;
+          const int k0 = w.inc_off[ends[e]], k1 = k0 + inc_cnt[ends[e]];
+          for (int k = k0; k < k1; ++k) {
+            const int o = w.inc[k];
+            if (o != u && prio_gt(hu, u, fmix32((uint32_t)o ^ w.seed), o))
+              atomicSub(&wait_lds[(o - u0) >> 1], 1u << (16 * ((o - u0) & 1)));
           }
         }
       }
-      if (ready) {
-        int c;
-        if (used == ~0ull) {
-          overflow = true;
-          c = kMaxColours - 1;
-        } else {
-          c = __ffsll((unsigned long long)~used) - 1;
-        }
-        if (in_lds)
-          col_lds[u - u0] = (signed char)c;
-        else
-          __hip_atomic_store(&w.cp_colour[u], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      } else {
-        pending = true;
-      }
+      if (!__syncthreads_or(todo != 0)) break;
     }
-    if (!__syncthreads_or(pending)) break;
+  } else {
+    for (;;) {
+      bool pending = false;
+      for (int u = u0 + tid; u < u1; u += kColBS) {
+        if (__hip_atomic_load(&w.cp_colour[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= 0) continue;
+        const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
+        uint64_t used = 0;
+        bool ready = true;
+        int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
+        for (int e = 0; e < 2 && ready; ++e) {
+          if (ends[e] < 0) continue;
+          const int k0 = w.inc_off[ends[e]], k1 = k0 + inc_cnt[ends[e]];
+          for (int k = k0; k < k1; ++k) {
+            int o = w.inc[k];
+            if (o == u) continue;
+            int co = __hip_atomic_load(&w.cp_colour[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (co >= 0) {
+              used |= 1ull << co;
+            } else if (prio_gt(fmix32((uint32_t)o ^ w.seed), o, hu, u)) {
+              ready = false;
+              break;
+            }
+          }
+        }
+        if (ready)
+          __hip_atomic_store(&w.cp_colour[u], pick(used), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          pending = true;
+      }
+      if (!__syncthreads_or(pending)) break;
+    }
   }
   if (__syncthreads_or(overflow) && tid == 0) atomicOr(&w.scal[SC_FLAGS], F_COLOUR_CAP);
-  if (in_lds)
-    for (int u = u0 + tid; u < u1; u += kColBS) w.cp_colour[u] = col_lds[u - u0];
+  if (in_lds)  // a copy left uncoloured by the round bound gets a valid colour (the step is flagged)
+    for (int u = u0 + tid; u < u1; u += kColBS) w.cp_colour[u] = col_lds[u - u0] < 0 ? kMaxColours - 1 : col_lds[u - u0];
   __syncthreads();
   // colour histogram and offsets
   if (tid < kMaxColours) {
