@@ -56,12 +56,17 @@ __global__ void k_cells(WP w) {
   atomicAdd(&w.bcount[b], 1);
 }
 
+// Bodies in bucket order, with a packed copy of what the neighbour scan reads
+// (cell, body; centre, radius), so a bucket is one or two cache lines.
 __global__ void k_scatter(WP w) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= w.N) return;
+  const int N = w.N;
   uint32_t b = w.bucket[i];
   int pos = w.bstart[b] + atomicAdd(&w.bfill[b], 1);
   w.bbody[pos] = i;
+  w.srt_cell[pos] = make_int4(w.cell[i], w.cell[N + i], w.cell[2 * N + i], i);
+  w.srt_pos[pos] = make_float4(w.st[i], w.st[N + i], w.st[2 * N + i], w.b_radius[i]);
 }
 
 // FP64 contact predicates, evaluated exactly as written (no contraction).
@@ -224,19 +229,21 @@ __device__ __forceinline__ void for_each_contact(const WP& w, int a, F&& f) {
         uint32_t h = cell_hash(s, nx, ny, nz) & (uint32_t)(w.T - 1);
         const int k1 = w.bstart[h + 1];
         for (int k = w.bstart[h]; k < k1; ++k) {
-          const int b = w.bbody[k];
-          if (b <= a) continue;
-          if (w.cell[b] != nx || w.cell[N + b] != ny || w.cell[2 * N + b] != nz || w.b_scene[b] != s) continue;
+          const int4 ck = w.srt_cell[k];
+          const int b = ck.w;
+          if (b <= a || ck.x != nx || ck.y != ny || ck.z != nz) continue;
+          if (w.b_scene[b] != s) continue;
           if (has_joints && jointed(w, a, b)) continue;
+          const float4 pr = w.srt_pos[k];
           const double hb = w.has_caps ? (double)w.b_half[b] : 0.0;
           bool hit;
           if (ha == 0.0 && hb == 0.0) {
-            hit = pred_spheres(xa, ya, za, ra, w.st[b], w.st[N + b], w.st[2 * N + b], w.b_radius[b], m, d);
+            hit = pred_spheres(xa, ya, za, ra, pr.x, pr.y, pr.z, pr.w, m, d);
           } else {
-            const double pb[3] = {w.st[b], w.st[N + b], w.st[2 * N + b]};
+            const double pb[3] = {pr.x, pr.y, pr.z};
             double ub[3] = {0.0, 0.0, 0.0};
             if (hb > 0.0) capsule_axis(w.st, N, b, ub);
-            hit = pred_swept(pa, ua, ha, ra, pb, ub, hb, w.b_radius[b], m, d, stp);
+            hit = pred_swept(pa, ua, ha, ra, pb, ub, hb, pr.w, m, d, stp);
           }
           if (hit) f((uint32_t)b << 1);
         }

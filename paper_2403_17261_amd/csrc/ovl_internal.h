@@ -94,7 +94,9 @@ struct WP {
   int32_t* bcount;              // [T+1]
   int32_t* bstart;              // [T+1]
   int32_t* bfill;               // [T]
-  int32_t* bbody;               // [N]
+  int32_t* bbody;               // [N] bodies in bucket order
+  int4* srt_cell;               // [N] bucket order: cell x, y, z and body
+  float4* srt_pos;              // [N] bucket order: centre and radius
   // contacts
   int32_t* ccount;              // [N+1]
   int32_t* coff;                // [N+1]

@@ -509,6 +509,8 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   wp.bstart = w->alloc<int32_t>(g, T + 1, ok);
   wp.bfill = w->alloc<int32_t>(g, T, ok);
   wp.bbody = w->alloc<int32_t>(g, Np, ok);
+  wp.srt_cell = w->alloc<int4>(g, Np, ok);
+  wp.srt_pos = w->alloc<float4>(g, Np, ok);
   wp.ccount = w->alloc<int32_t>(g, N + 1, ok);
   wp.c_keep = w->alloc<uint32_t>(g, (size_t)kKeep * Np, ok);
   wp.coff = w->alloc<int32_t>(g, N + 1, ok);
