@@ -808,6 +808,98 @@ static int32_t local_rep(const int32_t* prep, const int32_t* rep_body, int32_t p
   return (lo < prep[p + 1] && rep_body[lo] == v) ? lo - prep[p] : -1;
 }
 
+/* ------------------------------------------------------------------------- */
+/* dynamic load balancing (section 5.4): Alg. 6 with the bridge test Alg. 7  */
+/* ------------------------------------------------------------------------- */
+
+/* A worker's load is the number of bodies active in it; the load of a set of
+ * workers (Alg. 6 line 5) is read as the sum of its workers' loads.  Workers
+ * are the local partition bits of a scene; load[] is indexed by global id. */
+typedef struct {
+  uint64_t* mask;
+  int64_t* load;
+  const int32_t* pbase;
+  const int32_t* scene;
+} lb_state;
+
+static void lb_activate(lb_state* st, uint64_t set, int32_t v) {
+  uint64_t add = set & ~st->mask[v];
+  st->mask[v] |= add;
+  for (; add; add &= add - 1) st->load[st->pbase[st->scene[v]] + lowest_bit(add)]++;
+}
+
+static void lb_deactivate(lb_state* st, uint64_t set, int32_t v) {
+  uint64_t rem = set & st->mask[v];
+  st->mask[v] &= ~rem;
+  for (; rem; rem &= rem - 1) st->load[st->pbase[st->scene[v]] + lowest_bit(rem)]--;
+}
+
+static int64_t lb_set_load(const lb_state* st, uint64_t set, int s) {
+  int64_t l = 0;
+  for (; set; set &= set - 1) l += st->load[st->pbase[s] + lowest_bit(set)];
+  return l;
+}
+
+/* Alg. 7: a body bridges workers when its graph neighbours span more than one */
+static int lb_bridge(const lb_state* st, const graph* g, int32_t b) {
+  uint64_t w = 0;
+  for (int32_t k = g->off[b]; k < g->off[b + 1]; ++k) w |= st->mask[g->adj[k]];
+  return popcount64(w) > 1;
+}
+
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Alg. 6 over the new contacts, in key order.  Readings: ties in line 5 go to
+ * A's side (the test is <=); "smallest load" ties go to the lowest worker
+ * index; the BFS vertices of line 12 include the root. */
+static void load_balance(lb_state* st, const graph* g, const contact_list* cl, int64_t N, const uint64_t* prev,
+                         int64_t nprev, int depth, bfs_ws* ws) {
+  for (int64_t i = 0; i < cl->n; ++i) {
+    uint64_t key = cl->c[i].key;
+    int32_t A = (int32_t)(key >> 32);
+    int64_t B64 = (int64_t)((key >> 1) & 0x7fffffff);
+    if (B64 >= N) continue; /* statics are not in the graph */
+    if (nprev && bsearch(&key, prev, (size_t)nprev, sizeof(uint64_t), cmp_u64)) continue;
+    int32_t B = (int32_t)B64;
+    int s = st->scene[A];
+    uint64_t WA = st->mask[A], WB = st->mask[B];
+    if ((WA & WB) == 0) {
+      /* Fig. 9 (i), (ii): make one worker aware of the other body */
+      int32_t root;
+      if (lb_set_load(st, WA, s) <= lb_set_load(st, WB, s)) {
+        lb_activate(st, WA, B);
+        root = B;
+      } else {
+        lb_activate(st, WB, A);
+        root = A;
+      }
+      int64_t nv = bfs(g, root, depth, ws);
+      for (int64_t q = 0; q < nv; ++q) lb_activate(st, WA | WB, ws->queue[q]);
+    } else if (popcount64(WA) > 1 && popcount64(WB) == 1 && !lb_bridge(st, g, A)) {
+      lb_deactivate(st, WA & ~WB, A); /* Fig. 9 (iii), (iv) */
+    } else if (popcount64(WB) > 1 && popcount64(WA) == 1 && !lb_bridge(st, g, B)) {
+      lb_deactivate(st, WB & ~WA, B);
+    } else if (WA == WB) {
+      /* Fig. 9 (v): keep both bodies only in the least loaded of their workers */
+      int best = -1;
+      int64_t bl = 0;
+      for (uint64_t t = WA; t; t &= t - 1) {
+        int b = lowest_bit(t);
+        int64_t l = st->load[st->pbase[s] + b];
+        if (best < 0 || l < bl) {
+          best = b;
+          bl = l;
+        }
+      }
+      lb_deactivate(st, WA & ~(1ull << best), A);
+      lb_deactivate(st, WB & ~(1ull << best), B);
+    }
+  }
+}
+
 orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* owner,
                      const int32_t* parts_per_scene, const orc_params* prm, const orc_cache* cache,
                      const int32_t* forced_iters) {
@@ -891,15 +983,37 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
    * active in every partition that owns some body within k hops of it ---- */
   uint64_t* mask = (uint64_t*)xalloc((size_t)N * 8);
   int64_t n_overlap = 0;
-  for (int64_t v = 0; v < N; ++v) {
-    int64_t nv = bfs(&g, (int32_t)v, prm->halo_k, &ws);
-    uint64_t m = 0;
-    for (int64_t i = 0; i < nv; ++i) {
-      int32_t u = ws.queue[i];
-      m |= 1ull << (owner[u] - pbase[sc->scene[u]]);
+  if (prm->lb_masks) {
+    /* worker sets carried from the previous step, updated by Alg. 6 */
+    for (int64_t v = 0; v < N; ++v) {
+      mask[v] = prm->lb_masks[v];
+      if (mask[v] == 0 || (mask[v] >> parts_per_scene[sc->scene[v]]) != 0) {
+        snprintf(res->err, sizeof res->err, "body %lld: empty worker set or a bit beyond its scene's partitions",
+                 (long long)v);
+        stats[6] = 1;
+        free(mask);
+        return res;
+      }
     }
-    mask[v] = m;
-    if (popcount64(m) >= 2) n_overlap++;
+    int64_t* load = (int64_t*)xalloc((size_t)(G + 1) * 8);
+    for (int64_t v = 0; v < N; ++v)
+      for (uint64_t t = mask[v]; t; t &= t - 1) load[pbase[sc->scene[v]] + lowest_bit(t)]++;
+    lb_state st = {mask, load, pbase, sc->scene};
+    load_balance(&st, &g, &cl, N, prm->lb_prev_keys, prm->lb_n_prev, prm->lb_depth, &ws);
+    free(load);
+    for (int64_t v = 0; v < N; ++v)
+      if (popcount64(mask[v]) >= 2) n_overlap++;
+  } else {
+    for (int64_t v = 0; v < N; ++v) {
+      int64_t nv = bfs(&g, (int32_t)v, prm->halo_k, &ws);
+      uint64_t m = 0;
+      for (int64_t i = 0; i < nv; ++i) {
+        int32_t u = ws.queue[i];
+        m |= 1ull << (owner[u] - pbase[sc->scene[u]]);
+      }
+      mask[v] = m;
+      if (popcount64(m) >= 2) n_overlap++;
+    }
   }
   put(res, ORC_MASK, mask, N);
 

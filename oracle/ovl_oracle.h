@@ -44,6 +44,16 @@ typedef struct {
   int32_t learned;              /* 1: learned warm start for contacts, guarded per partition */
   const float* mlp;             /* [ORC_MLP_PARAMS] W1[12][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3] */
   const int32_t* forced_guard;  /* [G] or NULL: 1 learned, 0 plain, -1 decide */
+  /* Dynamic load balancing (section 5.4, Alg. 6-7).  lb_masks NULL: the
+   * worker sets are the k-hop halo of the owners.  Otherwise they are carried
+   * from the previous step (lb_masks, local partition bits per body) and the
+   * step updates them with the rules of Alg. 6 on its new contacts: the pairs
+   * of dynamic bodies in this step's list whose key is not in lb_prev_keys
+   * (the previous step's contact keys, ascending). */
+  const uint64_t* lb_masks;
+  const uint64_t* lb_prev_keys;
+  int64_t lb_n_prev;
+  int32_t lb_depth;             /* growth depth gamma of Alg. 6 (>= 0) */
 } orc_params;
 
 #define ORC_MLP_IN 12

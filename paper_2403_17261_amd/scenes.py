@@ -341,6 +341,24 @@ def config2(seed: int = 0, n: int = 20000) -> Scene:
     return sc
 
 
+def bowl_naive(n: int = 5040, seed: int = 0, n_parts: int = 7, scale: Optional[float] = None,
+               squeeze: float = 1.0) -> Scene:
+    """Bowl pile started from the naive division of section 5.4 (the body list
+    cut into equal runs, one per worker), for dynamic load balancing with
+    growth depth 0.  Default size: 5040 spheres and 7 workers.  ``squeeze`` < 1
+    pulls the drop positions towards the bowl's floor centre so that the pile
+    is in contact from the first step (small test cases)."""
+    if scale is None:
+        scale = (n / 20000.0) ** (1.0 / 3.0)
+    blk = bowl_scene(n, seed, n_parts, scale=scale)
+    if squeeze != 1.0:
+        st = blk["state"]
+        st[:, :3] *= np.float32(squeeze)
+        st[:, 2] += np.float32(0.5)
+    blk["owner"] = (np.arange(n, dtype=np.int64) * n_parts // max(n, 1)).astype(np.int32)
+    return _assemble([blk], f"bowl-naive-{n}", halo_k=0, beta=4, dt=1 / 60, iters=30, steps=1000)
+
+
 def chains_scene(n_chains=256, links=200, seed=0, n_parts=16, radius=0.1, mass=0.5,
                  x_extent=20.0, n_static=16):
     rng = _rng(seed)
