@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libovl.so")
-SOURCES = ["prim.hip", "collide.hip", "graph.hip", "solve.hip", "mlp.hip", "world.hip"]
+SOURCES = ["prim.hip", "collide.hip", "graph.hip", "balance.hip", "solve.hip", "mlp.hip", "world.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -383,17 +383,22 @@ hipError_t launch_graph(const WP& w, int32_t* sc, hipStream_t s) {
     k_adj_joints<<<nb, kBlock, 0, s>>>(w);
     if (w.Ccap > 0) k_adj_contacts<<<ncb, kBlock, 0, s>>>(w);
     k_adj_sort<<<nb, kBlock, 0, s>>>(w);
-    // overlap masks: k rounds of neighbour OR
-    k_mask_init<<<nb, kBlock, 0, s>>>(w);
-    uint64_t* a = w.mask;
-    uint64_t* b = w.mask_tmp;
-    for (int r = 0; r < w.halo_k; ++r) {
-      k_or_round<<<nb, kBlock, 0, s>>>(w, a, b);
-      uint64_t* t = a;
-      a = b;
-      b = t;
+    if (w.lb_on) {
+      // worker sets carried from the last step, updated from the new contacts
+      if ((e = launch_balance(w, sc, s))) return e;
+    } else {
+      // overlap masks: k rounds of neighbour OR
+      k_mask_init<<<nb, kBlock, 0, s>>>(w);
+      uint64_t* a = w.mask;
+      uint64_t* b = w.mask_tmp;
+      for (int r = 0; r < w.halo_k; ++r) {
+        k_or_round<<<nb, kBlock, 0, s>>>(w, a, b);
+        uint64_t* t = a;
+        a = b;
+        b = t;
+      }
+      if (a != w.mask) k_copy_u64<<<nb, kBlock, 0, s>>>(a, w.mask, w.N);
     }
-    if (a != w.mask) k_copy_u64<<<nb, kBlock, 0, s>>>(a, w.mask, w.N);
     k_rep_count<<<nb, kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }

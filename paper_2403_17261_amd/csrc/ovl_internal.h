@@ -18,6 +18,7 @@ constexpr int kPgsCfgBlock[kPgsCfgCount] = {1024, 512, 256, 256};
 constexpr int kPgsCfgReps[kPgsCfgCount] = {4800, 2400, 1200, 2400};
 constexpr int kBlock = 256;          // generic per-item kernels
 constexpr int kKeep = 16;            // contact keys per body kept between the two narrow-phase passes
+constexpr int kLbLdsCap = 12288;     // load balancing: scenes up to this many bodies keep their sets in LDS
 // warm-start network 12 -> 64 -> 64 -> 3
 constexpr int kMlpIn = 12, kMlpHid = 64, kMlpOut = 3;
 constexpr int kMlpParams = kMlpIn * kMlpHid + kMlpHid + kMlpHid * kMlpHid + kMlpHid + kMlpHid * kMlpOut + kMlpOut;
@@ -37,6 +38,7 @@ enum Scal {
   SC_NJCOPY,         // joint copies
   SC_NCCOPY,         // contact copies
   SC_NOVERLAP,       // bodies in >= 2 partitions
+  SC_LB_NPREV,       // contact keys carried for the load balancing (last committed step)
   SC_COUNT = 16
 };
 
@@ -186,6 +188,19 @@ struct WP {
   int64_t* stat_i64;            // [8]: 0 sum over steps of the largest sweep count, 1 unconverged partitions,
                                 //      2 algorithmic bytes of the sweeps, 3 sweeps summed over partitions,
                                 //      4 committed steps
+  // dynamic load balancing: worker sets carried from step to step
+  int32_t lb_on;                // 1: sets carried and updated from the new contacts; 0: k-hop halo
+  int32_t lb_depth;             // growth depth of the inter-worker rule
+  int32_t lb_lds_max;           // largest scene of at most kLbLdsCap bodies (LDS layout size), 0 if none
+  int32_t lb_big;               // 1: some scene has more than kLbLdsCap bodies
+  uint64_t* lb_mask;            // [N] sets of the last committed step
+  uint64_t* lb_prev;            // [>= Ccap] contact keys of the last committed step, ascending
+  int32_t* lb_cnt;              // [N+1] new contacts per first body
+  int32_t* lb_pos;              // [N+1] exclusive prefix of lb_cnt
+  int32_t* lb_flag;             // [Ccap] 1: the contact is new and joins two dynamic bodies
+  int32_t* lb_new;              // [Ccap] new contacts in key order
+  int32_t* lb_queue;            // [N] growth BFS queue of scenes kept in global memory
+  uint32_t* lb_visit;           // [N/32+1] growth BFS visited bits of scenes kept in global memory
   // scalars
   int32_t* scal;                // [SC_COUNT]
 };
@@ -224,6 +239,10 @@ constexpr int64_t kBytesDynDyn = 220;
 constexpr int64_t kBytesStatic = 164;
 constexpr int64_t kBytesJoint = 192;
 hipError_t pgs_set_attributes();
+// dynamic load balancing (between the graph and the replica table; commit after the blend)
+hipError_t launch_balance(const WP& w, int32_t* scan_scratch, hipStream_t s);
+hipError_t launch_balance_commit(const WP& w, hipStream_t s);
+hipError_t lb_set_attributes();
 hipError_t launch_mlp_world(const WP& w, hipStream_t s);
 void mlp_pack(const float* params, std::vector<uint16_t>& wb, std::vector<float>& bias);
 

@@ -1421,7 +1421,9 @@ hipError_t launch_solve_post(const WP& w, hipStream_t s, bool exact_residual) {
     if ((e = hipGetLastError())) return e;
   }
   k_commit<<<1, kCommitBS, 0, s>>>(w);
-  return hipGetLastError();
+  if ((e = hipGetLastError())) return e;
+  if (w.lb_on) return launch_balance_commit(w, s);
+  return hipSuccess;
 }
 
 // reset the impulses to the warm start (to time the solve again on the same inputs)

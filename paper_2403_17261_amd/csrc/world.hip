@@ -32,7 +32,7 @@ struct ovl_world {
   std::string err;
   ovl_params prm{};
   int32_t N = 0, S = 0, J = 0, P = 0, Q = 0, G = 0, T = 0;
-  std::vector<int32_t> body_off, joint_off, pps;
+  std::vector<int32_t> body_off, joint_off, pps, owner_local;
   std::vector<void*> static_allocs, cap_allocs, part_allocs;
   int32_t* scan_scratch = nullptr;
   bool forced_next = false;
@@ -52,6 +52,11 @@ struct ovl_world {
   int64_t pgs_launches = 0;
   uint16_t* mlp_wb = nullptr;
   float* mlp_bias = nullptr;
+  // dynamic load balancing: per-body buffers (allocated at the first enable) and
+  // the carried contact keys, whose capacity follows the contact capacity
+  std::vector<void*> lb_allocs;
+  void* lb_prev_buf = nullptr;
+  int32_t lb_cap = 0;
 
   hipEvent_t take_event() {
     if (!ev_pool.empty()) {
@@ -119,6 +124,8 @@ struct ovl_world {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     free_group(part_allocs);
     free_group(cap_allocs);
+    free_group(lb_allocs);
+    raw_free(lb_prev_buf);
     free_group(static_allocs);
   }
 
@@ -166,7 +173,53 @@ struct ovl_world {
     w.wc_key = alloc<uint64_t>(g, Mcap, ok);
     w.wc_val = alloc<float>(g, (size_t)4 * Mcap, ok);
     w.mc_blk[2] = alloc<int32_t>(g, (size_t)(nblocks(Ccap, 256) + 1) * 64, ok);
+    w.lb_flag = alloc<int32_t>(g, Ccap, ok);
+    w.lb_new = alloc<int32_t>(g, Ccap, ok);
+    return ok && (lb_prev_buf == nullptr || lb_reserve(Ccap));
+  }
+
+  // Carried contact keys: capacity >= n, the first lb_cap keys kept on growth.
+  bool lb_reserve(int64_t n) {
+    if (lb_prev_buf && n <= lb_cap) return true;
+    const int64_t cap = std::max<int64_t>({n, (int64_t)wp.Ccap, 1024});
+    void* nb = raw_alloc((size_t)cap * sizeof(uint64_t));
+    if (!nb) return false;
+    if (lb_prev_buf) {
+      if (hipMemcpyAsync(nb, lb_prev_buf, (size_t)lb_cap * sizeof(uint64_t), hipMemcpyDeviceToDevice, stream) !=
+              hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        raw_free(nb);
+        return false;
+      }
+      raw_free(lb_prev_buf);
+    }
+    lb_prev_buf = nb;
+    lb_cap = (int32_t)cap;
+    wp.lb_prev = (uint64_t*)nb;
+    return true;
+  }
+
+  bool lb_alloc() {
+    if (!lb_allocs.empty()) return true;
+    bool ok = true;
+    const size_t Np = std::max(N, 1);
+    wp.lb_mask = alloc<uint64_t>(lb_allocs, Np, ok);
+    wp.lb_cnt = alloc<int32_t>(lb_allocs, Np + 1, ok);
+    wp.lb_pos = alloc<int32_t>(lb_allocs, Np + 1, ok);
+    wp.lb_queue = alloc<int32_t>(lb_allocs, Np, ok);
+    wp.lb_visit = alloc<uint32_t>(lb_allocs, Np / 32 + 1, ok);
+    if (ok) ok = hipMemsetAsync(wp.lb_visit, 0, (Np / 32 + 1) * sizeof(uint32_t), stream) == hipSuccess &&
+                 hipStreamSynchronize(stream) == hipSuccess;
+    if (ok) ok = lb_reserve(wp.Ccap);
+    if (!ok) free_group(lb_allocs);
     return ok;
+  }
+
+  // carried sets = owners' singletons (the naive start of section 5.4), no carried keys
+  bool lb_reset_to_owners(const std::vector<int32_t>& local) {
+    std::vector<uint64_t> m(std::max(N, 1), 0);
+    for (int i = 0; i < N; ++i) m[i] = 1ull << local[i];
+    return upload(wp.lb_mask, m.data(), (size_t)N * sizeof(uint64_t)) && write_scal(SC_LB_NPREV, 0);
   }
 
   bool alloc_parts(int32_t G_) {
@@ -298,8 +351,22 @@ struct ovl_world {
     int32_t M = std::max(wp.Mcap, (int32_t)std::ceil(1.5 * sc[SC_NCOPY]) + 1024);
     M = std::max(M, 2 * (C + J) + 1024);
     if (hipStreamSynchronize(stream) != hipSuccess) return false;
-    free_group(cap_allocs);
-    return alloc_caps(C, M, R, A);
+    // the warm-start cache of the last committed step moves to the new buffers
+    const WP old = wp;
+    const int64_t keep = std::min(sc[SC_PREV_NCOPY], old.Mcap);
+    std::vector<void*> old_allocs;
+    old_allocs.swap(cap_allocs);
+    bool ok = alloc_caps(C, M, R, A);
+    auto d2d = [&](void* dst, const void* src, size_t bytes) {
+      ok = ok && (bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream) == hipSuccess);
+    };
+    d2d(wp.wc_part, old.wc_part, keep * sizeof(int32_t));
+    d2d(wp.wc_kind, old.wc_kind, keep * sizeof(int32_t));
+    d2d(wp.wc_key, old.wc_key, keep * sizeof(uint64_t));
+    for (int k = 0; k < 4; ++k) d2d(wp.wc_val + (size_t)k * wp.Mcap, old.wc_val + (size_t)k * old.Mcap, keep * sizeof(float));
+    ok = ok && hipStreamSynchronize(stream) == hipSuccess;
+    free_group(old_allocs);
+    return ok;
   }
 };
 
@@ -371,6 +438,8 @@ ovl_status set_partitions_impl(ovl_world* w, const int32_t* owner, const int32_t
   w->pps.assign(pps, pps + S);
   w->wp.halo_k = halo_k;
   w->wp.beta = beta;
+  w->owner_local.assign(local.begin(), local.end());
+  if (w->wp.lb_on && !w->lb_reset_to_owners(w->owner_local)) return w->fail(OVL_ERR_DEVICE, "upload failed");
   return OVL_OK;
 }
 
@@ -479,6 +548,13 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   wp.T = T;
   wp.cs = std::max(1.02f * (2.0f * rmax + mmax), 1e-3f);
   wp.has_caps = has_caps ? 1 : 0;
+  for (int s = 0; s < S; ++s) {
+    const int ns = body_off[s + 1] - body_off[s];
+    if (ns <= kLbLdsCap)
+      wp.lb_lds_max = std::max(wp.lb_lds_max, ns);
+    else
+      wp.lb_big = 1;
+  }
   w->set_params(*params);
   bool ok = true;
   auto& g = w->static_allocs;
@@ -597,7 +673,7 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   }
   static bool attrs = false;
   if (!attrs) {
-    if (pgs_set_attributes() != hipSuccess) {
+    if (pgs_set_attributes() != hipSuccess || lb_set_attributes() != hipSuccess) {
       delete w;
       g_create_error = "could not raise the LDS limit of the solver kernel";
       return OVL_ERR_DEVICE;
@@ -644,6 +720,38 @@ ovl_status ovl_set_partitions(ovl_world* w, const int32_t* owner, int64_t n_bodi
   if (n_bodies != w->N || n_scenes != w->S) return w->fail(OVL_ERR_INVALID_ARG, "n_bodies/n_scenes mismatch");
   if ((w->N > 0 && !owner) || !parts_per_scene) return w->fail(OVL_ERR_INVALID_ARG, "NULL array");
   return set_partitions_impl(w, owner, parts_per_scene, halo_k, beta);
+}
+
+ovl_status ovl_set_load_balance(ovl_world* w, int32_t enable, int32_t depth, const uint64_t* sets,
+                                int64_t n_sets, const uint64_t* prev_keys, int64_t n_prev) {
+  if (!w) return OVL_ERR_INVALID_ARG;
+  if (enable != 0 && enable != 1) return w->fail(OVL_ERR_INVALID_ARG, "enable must be 0 or 1");
+  if (!enable) {
+    w->wp.lb_on = 0;
+    return OVL_OK;
+  }
+  if (depth < 0 || depth > 64) return w->fail(OVL_ERR_INVALID_ARG, "depth must be in [0,64]");
+  if (sets && n_sets != w->N) return w->fail(OVL_ERR_INVALID_ARG, "sets must have n_bodies entries");
+  if (n_prev < 0 || (n_prev > 0 && !prev_keys)) return w->fail(OVL_ERR_INVALID_ARG, "bad prev_keys");
+  if (n_prev > (int64_t)1 << 30) return w->fail(OVL_ERR_INVALID_ARG, "too many prev_keys");
+  if (sets)
+    for (int s = 0; s < w->S; ++s)
+      for (int i = w->body_off[s]; i < w->body_off[s + 1]; ++i)
+        if (sets[i] == 0 || (w->pps[s] < 64 && (sets[i] >> w->pps[s]) != 0))
+          return w->fail(OVL_ERR_INVALID_ARG, "set of body " + std::to_string(i) +
+                                                  " is empty or names a partition outside its scene");
+  for (int64_t i = 1; i < n_prev; ++i)
+    if (prev_keys[i] <= prev_keys[i - 1])
+      return w->fail(OVL_ERR_INVALID_ARG, "prev_keys must be strictly increasing");
+  if (hipStreamSynchronize(w->stream) != hipSuccess) return w->fail(OVL_ERR_DEVICE, "sync failed");
+  if (!w->lb_alloc() || !w->lb_reserve(n_prev)) return w->fail(OVL_ERR_OOM, "load-balancing buffers");
+  bool ok = sets ? w->upload(w->wp.lb_mask, sets, (size_t)w->N * sizeof(uint64_t)) : w->lb_reset_to_owners(w->owner_local);
+  ok = ok && w->upload(w->wp.lb_prev, prev_keys, (size_t)n_prev * sizeof(uint64_t)) &&
+       w->write_scal(SC_LB_NPREV, (int32_t)n_prev);
+  if (!ok || hipStreamSynchronize(w->stream) != hipSuccess) return w->fail(OVL_ERR_DEVICE, "upload failed");
+  w->wp.lb_on = 1;
+  w->wp.lb_depth = depth;
+  return OVL_OK;
 }
 
 ovl_status ovl_force_iters(ovl_world* w, const int32_t* iters, int32_t n_parts) {
@@ -710,7 +818,6 @@ ovl_status ovl_step(ovl_world* w, int32_t n_steps, ovl_step_stats* stats, int32_
     int done = sc[SC_COMMITTED] - committed0;
     if (!w->grow(sc)) return w->fail(OVL_ERR_OOM, "could not grow the per-step buffers");
     w->write_scal(SC_FLAGS, 0);
-    w->write_scal(SC_PREV_NCOPY, 0);
     if (forced && done == 0) {
       (void)ovl_force_iters(w, saved_force.data(), w->G);
     }
@@ -897,7 +1004,6 @@ ovl_status ovl_autotune(ovl_world* w, int32_t trials, ovl_launch_cfg* chosen, fl
     if (!(sc[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP))) break;
     if (attempt > 0 || !w->grow(sc)) return take_flags(w, sc[SC_FLAGS]);
     w->write_scal(SC_FLAGS, 0);
-    w->write_scal(SC_PREV_NCOPY, 0);
   }
   if (sc[SC_FLAGS]) return take_flags(w, sc[SC_FLAGS]);
   const ovl_launch_cfg keep = w->launch;

@@ -57,8 +57,11 @@ def check_state(sc, gpu, ref, dt, label=""):
 
 
 def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, forced=None, label="",
-                 check_lambda0=True):
-    """One GPU step from the world's current state against one oracle step from the same inputs."""
+                 check_lambda0=True, lb=None):
+    """One GPU step from the world's current state against one oracle step from the same inputs.
+
+    lb: None (k-hop halo sets), or dict(sets=, prev=, depth=) giving the carried
+    worker sets and previous contact keys the world was given for this step."""
     halo_k = sc.halo_k if halo_k is None else halo_k
     beta = sc.beta if beta is None else beta
     owner = sc.owner if owner is None else owner
@@ -73,6 +76,9 @@ def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, fo
                                  "copy_colour", "copy_lambda0", "part_iters")}
     gs = w.read_state()
     kw = oracle_kwargs(sc, params, halo_k, beta)
+    if lb is not None:
+        kw.update(lb_masks=np.asarray(lb["sets"], np.uint64), lb_prev_keys=np.asarray(lb["prev"], np.uint64),
+                  lb_depth=int(lb["depth"]))
     o = oracle.step(sc, state=s0, owner=owner, parts_per_scene=pps, cache=cache,
                     forced_iters=forced if forced is not None else None, **kw)
     log(f"  {label} contacts={len(o['contact_key'])} copies={len(o['copy_key'])} replicas={len(o['rep_body'])} "
@@ -87,8 +93,14 @@ def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, fo
     for k in ("part_copy_off", "copy_kind", "copy_key", "copy_ia", "copy_ib", "copy_colour"):
         assert np.array_equal(g[k], o[k]), f"{k} differs"
     if check_lambda0 and len(o["copy_lambda0"]):
-        d0 = np.abs(g["copy_lambda0"] - o["copy_lambda0"]).max()
+        diff = np.abs(g["copy_lambda0"] - o["copy_lambda0"])
+        d0 = diff.max()
         scale = max(1.0, np.abs(o["copy_lambda0"]).max())
+        if d0 > 1e-5 * scale:
+            bad = np.nonzero(diff.max(axis=1) > 1e-5 * scale)[0]
+            u = int(bad[0])
+            log(f"  warm start: {len(bad)} copies beyond {1e-5 * scale:.3e}; first uid {u} kind {g['copy_kind'][u]} "
+                f"key {int(g['copy_key'][u]):#x} gpu {g['copy_lambda0'][u]} oracle {o['copy_lambda0'][u]}")
         assert d0 <= 1e-5 * scale, f"warm start differs by {d0}"
     if forced is None and not params.mode:
         assert np.all(g["part_iters"] == params.max_iters)
