@@ -64,7 +64,7 @@ class _Params(C.Structure):
                 ("adaptive", C.c_int32), ("warmstart", C.c_int32), ("halo_k", C.c_int32), ("beta", C.c_int32),
                 ("brute_force_contacts", C.c_int32), ("seed", C.c_uint32), ("learned", C.c_int32),
                 ("mlp", C.c_void_p), ("forced_guard", C.c_void_p), ("lb_masks", C.c_void_p),
-                ("lb_prev_keys", C.c_void_p), ("lb_n_prev", C.c_int64), ("lb_depth", C.c_int32)]
+                ("lb_depth", C.c_int32)]
 
 
 class _Cache(C.Structure):
@@ -154,7 +154,7 @@ def mlp_infer(params, x12):
 
 DEFAULTS = dict(dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), cfm=0.0, erp=0.2, max_iters=20, tol=1e-4,
                 adaptive=False, warmstart=True, halo_k=1, beta=4, seed=0, brute_force=False, mlp=None,
-                forced_guard=None, lb_masks=None, lb_prev_keys=None, lb_depth=0)
+                forced_guard=None, lb_masks=None, lb_depth=0)
 
 
 def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced_iters=None, **kw):
@@ -199,9 +199,6 @@ def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced
         pr.forced_guard = _ptr(arr(p["forced_guard"], np.int32))
     if p["lb_masks"] is not None:
         pr.lb_masks = _ptr(arr(p["lb_masks"], np.uint64))
-        prev = np.sort(np.asarray(p["lb_prev_keys"] if p["lb_prev_keys"] is not None else [], np.uint64))
-        pr.lb_prev_keys = _ptr(arr(prev, np.uint64)) if prev.size else None
-        pr.lb_n_prev = int(prev.size)
         pr.lb_depth = int(p["lb_depth"])
     cp = None
     if cache is not None and len(cache["cache_part"]):
@@ -250,18 +247,17 @@ def initial_masks(scene, owner=None):
     return (np.uint64(1) << (own - pbase[np.asarray(scene.scene)]).astype(np.uint64)).astype(np.uint64)
 
 
-def run_lb(scene, steps: int, depth: int, state=None, masks=None, prev_keys=None, cache=None, **kw):
+def run_lb(scene, steps: int, depth: int, state=None, masks=None, cache=None, **kw):
     """Several steps with dynamic load balancing (section 5.4, Alg. 1 with Alg. 6):
-    the worker sets and the contact keys are carried from step to step.
-    Returns (state, last output, per-step outputs' masks)."""
+    the worker sets are carried from step to step.
+    Returns (state, last output, the sets after every step)."""
     st = scene.state if state is None else state
     m = initial_masks(scene) if masks is None else masks
-    prev = np.zeros(0, np.uint64) if prev_keys is None else prev_keys
     out, hist = None, []
     for _ in range(steps):
-        out = step(scene, state=st, cache=cache, lb_masks=m, lb_prev_keys=prev, lb_depth=depth, **kw)
+        out = step(scene, state=st, cache=cache, lb_masks=m, lb_depth=depth, **kw)
         st = out["state"].astype(np.float32)
-        m, prev, cache = out["mask"].astype(np.uint64), out["contact_key"].astype(np.uint64), out
+        m, cache = out["mask"].astype(np.uint64), out
         hist.append(m)
     return st, out, hist
 

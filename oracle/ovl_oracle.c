@@ -847,22 +847,15 @@ static int lb_bridge(const lb_state* st, const graph* g, int32_t b) {
   return popcount64(w) > 1;
 }
 
-static int cmp_u64(const void* a, const void* b) {
-  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
-  return (x > y) - (x < y);
-}
-
-/* Alg. 6 over the new contacts, in key order.  Readings: ties in line 5 go to
- * A's side (the test is <=); "smallest load" ties go to the lowest worker
+/* Alg. 6 over the step's contacts, in key order.  Readings: ties in line 5 go
+ * to A's side (the test is <=); "smallest load" ties go to the lowest worker
  * index; the BFS vertices of line 12 include the root. */
-static void load_balance(lb_state* st, const graph* g, const contact_list* cl, int64_t N, const uint64_t* prev,
-                         int64_t nprev, int depth, bfs_ws* ws) {
+static void load_balance(lb_state* st, const graph* g, const contact_list* cl, int64_t N, int depth, bfs_ws* ws) {
   for (int64_t i = 0; i < cl->n; ++i) {
     uint64_t key = cl->c[i].key;
     int32_t A = (int32_t)(key >> 32);
     int64_t B64 = (int64_t)((key >> 1) & 0x7fffffff);
     if (B64 >= N) continue; /* statics are not in the graph */
-    if (nprev && bsearch(&key, prev, (size_t)nprev, sizeof(uint64_t), cmp_u64)) continue;
     int32_t B = (int32_t)B64;
     int s = st->scene[A];
     uint64_t WA = st->mask[A], WB = st->mask[B];
@@ -999,7 +992,7 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
     for (int64_t v = 0; v < N; ++v)
       for (uint64_t t = mask[v]; t; t &= t - 1) load[pbase[sc->scene[v]] + lowest_bit(t)]++;
     lb_state st = {mask, load, pbase, sc->scene};
-    load_balance(&st, &g, &cl, N, prm->lb_prev_keys, prm->lb_n_prev, prm->lb_depth, &ws);
+    load_balance(&st, &g, &cl, N, prm->lb_depth, &ws);
     free(load);
     for (int64_t v = 0; v < N; ++v)
       if (popcount64(mask[v]) >= 2) n_overlap++;

@@ -47,12 +47,11 @@ typedef struct {
   /* Dynamic load balancing (section 5.4, Alg. 6-7).  lb_masks NULL: the
    * worker sets are the k-hop halo of the owners.  Otherwise they are carried
    * from the previous step (lb_masks, local partition bits per body) and the
-   * step updates them with the rules of Alg. 6 on its new contacts: the pairs
-   * of dynamic bodies in this step's list whose key is not in lb_prev_keys
-   * (the previous step's contact keys, ascending). */
+   * step updates them with the rules of Alg. 6 applied to every contact of
+   * the step between two dynamic bodies, in key order (Alg. 1 passes the
+   * step's whole contact list; a contact handled by the first rule in one
+   * step meets the third rule in the next). */
   const uint64_t* lb_masks;
-  const uint64_t* lb_prev_keys;
-  int64_t lb_n_prev;
   int32_t lb_depth;             /* growth depth gamma of Alg. 6 (>= 0) */
 } orc_params;
 

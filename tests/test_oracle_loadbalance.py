@@ -3,22 +3,25 @@ bridge test of Alg. 7) against the scenarios of Figure 9, worked by hand.
 
 Each case places a few unit spheres on a line so that exactly the listed pairs
 touch, gives every body a worker set, and reads the worker sets the oracle
-hands to the rest of the step.  The expected sets follow from the text of
-section 5.4 and from the readings the oracle states (load of a body set = the
-number of bodies active in it, summed over its workers; ties go to A's side
-and to the lowest worker index; the BFS of the growth step includes its root):
+hands to the rest of the step.  Every contact of the step between two dynamic
+bodies is taken, in key order (Alg. 1 hands the step's contact list to Alg. 6,
+and the text has an isolated collision of one step become scenario (iii) in
+the next).  The expected sets follow from the text of section 5.4 and from the
+readings the oracle states (load of a set of workers = the number of bodies
+active in it, summed over its workers; ties go to A's side and to the lowest
+worker index; the BFS of the growth step includes its root):
 
 * (i)   inter-worker collision in isolation: the lighter side's workers are
         activated on the other body, nothing is taken away;
-* (ii)  the same with a body already touching others: growth to depth gamma;
+* (ii)  the same with a body already touching others: growth to depth gamma,
+        then the remaining contacts of the chain, depths 0 to 3;
 * (iii) an overlap body hit by a single-worker body with no other neighbour
         drops its other workers;
 * (iv)  the same when the overlap body bridges two workers: nothing changes;
 * (v)   two overlap bodies with the same workers keep only the least loaded;
-* contacts already present in the previous step change nothing;
+* (i) followed by (iii) in the next step: the body ends in one worker;
 * contacts are taken in key order and loads change as they are taken;
-* statics never take part;
-* with no new contacts the carried sets are the step's sets unchanged.
+* statics never take part.
 """
 import numpy as np
 import pytest
@@ -41,9 +44,8 @@ def _scene(xs, owner, n_parts, planes=None):
                                  dt=1 / 60.0, iters=10)
 
 
-def _masks(sc, masks, prev_pairs=(), depth=0):
-    prev = np.array([_key(a, b) for a, b in prev_pairs], np.uint64)
-    out = oracle.step(sc, lb_masks=np.asarray(masks, np.uint64), lb_prev_keys=prev, lb_depth=depth)
+def _masks(sc, masks, depth=0, state=None):
+    out = oracle.step(sc, state=state, lb_masks=np.asarray(masks, np.uint64), lb_depth=depth)
     return [int(m) for m in out["mask"]], out
 
 
@@ -74,20 +76,25 @@ def test_scenario_i_lighter_side_is_activated_on_the_other_body():
 
 
 def test_scenario_ii_growth_to_depth_gamma():
-    # chain A(0) - B(1) - C(1) - D(1) - E(1); only A-B is new; worker 0 lighter
+    # chain A(0) - B(1) - C(1) - D(1) - E(1), contacts (0,1), (1,2), (2,3), (3,4)
     xs = [i * STEP for i in range(5)]
     own = [0, 1, 1, 1, 1]
     sc = _scene(xs, own, 2)
-    old = [(1, 2), (2, 3), (3, 4)]
     expect = {
-        0: [0b01, 0b11, 0b10, 0b10, 0b10],   # B alone enters worker 0
-        1: [0b11, 0b11, 0b11, 0b10, 0b10],   # B's neighbours A and C join both
-        2: [0b11, 0b11, 0b11, 0b11, 0b10],   # D at two hops
-        3: [0b11, 0b11, 0b11, 0b11, 0b11],
+        # (0,1): B enters worker 0; (1,2): B bridges A and C, kept; the rest single-worker
+        0: [0b01, 0b11, 0b10, 0b10, 0b10],
+        # (0,1): A, B, C in both (loads 3 : 5); (1,2): B, C keep worker 0 (3 : 3);
+        # (2,3): tie, D enters worker 0 and C, D, E grow to both (5 : 4); (3,4): D, E keep worker 1
+        1: [0b11, 0b01, 0b11, 0b10, 0b10],
+        # (0,1): A..D in both (4 : 5); (1,2): B, C keep worker 0 (4 : 3); (2,3), (3,4): D bridges
+        2: [0b11, 0b01, 0b01, 0b11, 0b10],
+        # (0,1): all in both (5 : 5); (1,2): tie, B, C keep worker 0 (5 : 3); (2,3): D bridges;
+        # (3,4): D, E keep worker 1
+        3: [0b11, 0b01, 0b01, 0b10, 0b10],
     }
     for depth, want in expect.items():
-        m, out = _masks(sc, [1 << o for o in own], prev_pairs=old, depth=depth)
-        assert _touching(out) == [(0, 1)] + old
+        m, out = _masks(sc, [1 << o for o in own], depth=depth)
+        assert _touching(out) == [(0, 1), (1, 2), (2, 3), (3, 4)]
         assert m == want, depth
 
 
@@ -102,12 +109,12 @@ def test_scenario_iii_overlap_body_without_other_neighbours_leaves():
 
 
 def test_scenario_iv_bridge_body_is_kept():
-    # A(0) - B(0,1) - C(1): A-B new, B-C old; B's neighbours span both workers
+    # A(0) - B(0,1) - C(1): B's neighbours span both workers, both contacts keep it
     sc = _scene([0.0, STEP, 2 * STEP], [0, 0, 1], 2)
     masks = [0b01, 0b11, 0b10]
-    m, _ = _masks(sc, masks, prev_pairs=[(1, 2)])
+    m, _ = _masks(sc, masks)
     assert m == masks
-    # without C's contact B is no bridge any more and drops worker 1
+    # without C's contact B is no bridge and drops worker 1
     sc2 = _scene([0.0, STEP, 50.0], [0, 0, 1], 2)
     m, _ = _masks(sc2, masks)
     assert m == [0b01, 0b01, 0b10]
@@ -128,13 +135,15 @@ def test_scenario_v_two_overlap_bodies_keep_the_least_loaded_worker():
     assert m == [0b010, 0b010, 1, 1, 1]
 
 
-def test_old_contacts_change_nothing():
+def test_isolated_collision_becomes_scenario_iii_next_step():
+    # step 1: (i), a tie, so worker 0 is activated on B; step 2: the same contact
+    # is (iii) and B, touching nothing else, keeps only worker 0
     sc = _scene([0.0, STEP], [0, 1], 2)
-    m, _ = _masks(sc, [1, 2], prev_pairs=[(0, 1)])
-    assert m == [1, 2]
-    sc = _scene([0.0, STEP], [0, 1], 2)
-    m, _ = _masks(sc, [0b11, 0b11], prev_pairs=[(0, 1)])
-    assert m == [0b11, 0b11]
+    m1, o1 = _masks(sc, [1, 2])
+    assert m1 == [0b01, 0b11]
+    m2, o2 = _masks(sc, m1, state=o1["state"].astype(np.float32))
+    assert _touching(o2) == [(0, 1)]
+    assert m2 == [0b01, 0b01]
 
 
 def test_contacts_are_taken_in_key_order_with_running_loads():
@@ -164,16 +173,6 @@ def test_statics_take_no_part():
     assert len(out["contact_key"]) == 1 and m == [0b11]
 
 
-def test_no_new_contacts_keeps_the_carried_sets():
-    sc = scenes.config1()
-    o = oracle.step(sc)
-    keys = o["contact_key"].astype(np.uint64)
-    m = o["mask"].astype(np.uint64)
-    o2 = oracle.step(sc, lb_masks=m, lb_prev_keys=keys, lb_depth=2)
-    assert np.array_equal(o2["mask"], m)
-    assert np.array_equal(o2["state"], o["state"])
-
-
 def test_rejects_empty_or_out_of_range_sets():
     sc = _scene([0.0, STEP], [0, 1], 2)
     with pytest.raises(RuntimeError):
@@ -184,31 +183,23 @@ def test_rejects_empty_or_out_of_range_sets():
 
 def test_several_steps_keep_sets_valid():
     """Over a settling pile the sets stay non-empty and within the scene's
-    workers, every worker keeps bodies, and the changes happen only where new
-    contacts were (bodies away from every new contact keep their set)."""
+    workers, every worker keeps bodies, and a body with no dynamic contact
+    keeps its set."""
     sc = scenes.bowl_naive(300, 7, 4, squeeze=0.35)
-    st, prev, m = sc.state, np.zeros(0, np.uint64), oracle.initial_masks(sc)
+    st, m = sc.state, oracle.initial_masks(sc)
     changed_steps = 0
     for t in range(12):
-        out = oracle.step(sc, state=st, lb_masks=m, lb_prev_keys=prev, lb_depth=1)
+        out = oracle.step(sc, state=st, lb_masks=m, lb_depth=1)
         m2 = out["mask"].astype(np.uint64)
         assert (m2 != 0).all() and (m2 >> np.uint64(4) == 0).all()
         keys = out["contact_key"].astype(np.uint64)
-        new = keys[~np.isin(keys, prev)]
-        a = (new >> np.uint64(32)).astype(np.int64)
-        b = ((new >> np.uint64(1)) & np.uint64(0x7FFFFFFF)).astype(np.int64)
+        a = (keys >> np.uint64(32)).astype(np.int64)
+        b = ((keys >> np.uint64(1)) & np.uint64(0x7FFFFFFF)).astype(np.int64)
         dyn = b < sc.n_bodies
-        # bodies within one hop (depth 1) of a new dynamic contact's bodies
-        near = np.zeros(sc.n_bodies, bool)
-        near[a[dyn]] = near[b[dyn]] = True
-        ka = (keys >> np.uint64(32)).astype(np.int64)
-        kb = ((keys >> np.uint64(1)) & np.uint64(0x7FFFFFFF)).astype(np.int64)
-        kd = kb < sc.n_bodies
-        hop = near.copy()
-        hop[kb[kd][near[ka[kd]]]] = True
-        hop[ka[kd][near[kb[kd]]]] = True
-        assert np.array_equal(m2[~hop], m[~hop])
+        touched = np.zeros(sc.n_bodies, bool)
+        touched[a[dyn]] = touched[b[dyn]] = True
+        assert np.array_equal(m2[~touched], m[~touched])
         changed_steps += int((m2 != m).any())
-        st, prev, m = out["state"].astype(np.float32), np.sort(keys), m2
+        st, m = out["state"].astype(np.float32), m2
     load = [int(((m >> np.uint64(b)) & np.uint64(1)).sum()) for b in range(4)]
     assert min(load) > 0 and changed_steps > 0
