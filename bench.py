@@ -11,6 +11,12 @@ residual of 1e-4 m/s with a cap of 1000, 300 steps from the initial state
 --workload bowl: the 20,000-sphere bowl pile (8 k-means partitions recomputed
 every 10 steps, 2-hop overlap), 1000 steps.
 
+--workload bowl-lb: the paper's Bowl scene with dynamic load balancing
+(section 5.4): 5,040 spheres dropped into the bowl, 7 workers starting from
+the naive division of the body list, growth depth 0, worker sets updated from
+every step's new contacts; first 600 steps.  Also reports the per-worker body
+and contact distributions over the run and the same run without balancing.
+
 --workload batched: 512 independent bowl scenes (log-uniform 200..5000
 spheres, 1..6 k-means partitions each, fixed at the start), 30 sweeps per
 step, all in one world: the autotuned, graph-replayed launch against the
@@ -183,6 +189,130 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_bowl_lb(args):
+    """The Bowl scene of section 6 with the load balancing of section 5.4."""
+    import torch
+
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    sc = scenes.bowl_naive(5040, 0, 7)
+    steps = args.steps or 600
+    G = int(sc.parts_per_scene[0])
+    p = ovl.make_params(dt=sc.dt, max_iters=args.cap, mode=ovl.MODE_ADAPTIVE, tol=args.tol,
+                        warmstart=ovl.WARM_PLAIN)
+
+    def restart(w, lb):
+        w.write_state(sc.state, keep_cache=False)
+        w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=1, beta=sc.beta)
+        w.set_load_balance(lb, 0)
+
+    def timed_run(lb):
+        w = ovl.World(sc, p)
+        restart(w, lb)
+        log(f"[bowl-lb {'on' if lb else 'off'}] warm-up: the {steps} steps once (buffers grow here)")
+        w.step(steps, stats=True)
+        restart(w, lb)
+        w.profile(True)
+        c0 = w.counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w.step(steps)
+        w.sync()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        c1 = w.counters()
+        if c1["steps"] - c0["steps"] != steps:
+            raise RuntimeError("not every step committed")
+        r = {"secs": secs, "value": sc.n_bodies * steps / secs, "ms_per_step": 1e3 * secs / steps,
+             "pgs_ms": c1["pgs_ms"] - c0["pgs_ms"], "pgs_launches": c1["pgs_launches"] - c0["pgs_launches"],
+             "pgs_bytes": c1["pgs_bytes"] - c0["pgs_bytes"],
+             "sweeps_mean": (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / steps,
+             "unconverged": c1["unconverged_total"] - c0["unconverged_total"]}
+        log(f"[bowl-lb {'on' if lb else 'off'}] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step, "
+            f"sweeps/step {r['sweeps_mean']:.1f}")
+        return w, r
+
+    w, on = timed_run(True)
+    # per-worker distributions (Figures 13 and 14): the same trajectory again, sampled every 10 steps
+    restart(w, True)
+    bodies, contacts, overlap = [], [], []
+    for t in range(0, steps, 10):
+        w.step(10)
+        ro = w.debug("part_rep_off").astype(np.int64)
+        co = w.debug("part_copy_off").astype(np.int64)
+        bodies.append(np.diff(ro))
+        contacts.append(np.diff(co))
+        overlap.append(int((np.bitwise_count(w.debug("mask").astype(np.uint64)) >= 2).sum()))
+    w.close()
+    bodies, contacts = np.array(bodies), np.array(contacts)
+    half = len(bodies) // 2
+
+    def quart(x):
+        return [[int(v) for v in np.percentile(x[:, g], [25, 50, 75])] for g in range(G)]
+
+    def imbalance(x):
+        m = x.mean(axis=1)
+        ok = m > 0
+        return float(np.mean(x.max(axis=1)[ok] / m[ok])) if ok.any() else None
+
+    _, off = timed_run(False)
+    pgs_ms, pgs_launches, pgs_bytes = on["pgs_ms"], on["pgs_launches"], on["pgs_bytes"]
+    achieved = pgs_bytes / (pgs_ms * 1e-3) / 1e9 if pgs_ms > 0 else 0.0
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_lb(sc, args.tol, args.cap)
+    out = {
+        "metric": "body-steps/s at PGS residual <=1e-4, dynamic load balancing",
+        "value": on["value"], "unit": "body-steps/s", "n_gpus": 1, "steps": steps, "warmup": steps,
+        "ms_per_step": on["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": (f"bowl with load balancing: {sc.n_bodies} spheres r~U(0.2,0.5) m, density 1000, "
+                         f"five-plane bowl, mu 0.6, h 1/60 s, {G} workers from the naive division of the body "
+                         f"list, growth depth 0, beta 4, adaptive sweeps to {args.tol:g} (cap {args.cap}), "
+                         f"first {steps} steps of the drop"),
+            "mean_sweeps_per_step": round(on["sweeps_mean"], 2), "unconverged_partition_steps": int(on["unconverged"]),
+            "bodies_per_worker_quartiles_second_half": quart(bodies[half:]),
+            "contact_copies_per_worker_quartiles_second_half": quart(contacts[half:]),
+            "max_over_mean_bodies_second_half": imbalance(bodies[half:]),
+            "max_over_mean_contacts_second_half": imbalance(contacts[half:]),
+            "overlap_bodies_last": overlap[-1],
+            "without_balancing": {"ms_per_step": off["ms_per_step"], "body_steps_per_s": off["value"],
+                                  "sweeps_per_step": round(off["sweeps_mean"], 2),
+                                  "note": "same owners, 1-hop halo of the naive division every step"},
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_pgs (coloured projected Gauss-Seidel, one workgroup per partition)",
+            "launches": int(pgs_launches), "ms_per_launch": pgs_ms / max(1, pgs_launches),
+            "alg_bytes_per_launch": pgs_bytes / max(1, pgs_launches),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_lb(sc, tol, cap, n_steps=100):
+    """The oracle on the first n_steps steps of the same run (carried sets and keys)."""
+    import oracle
+
+    st, m, prev, o = sc.state, oracle.initial_masks(sc), np.zeros(0, np.uint64), None
+    t0 = time.perf_counter()
+    sweeps = 0
+    for _ in range(n_steps):
+        o = oracle.step(sc, state=st, cache=o, lb_masks=m, lb_prev_keys=prev, lb_depth=0, adaptive=True, tol=tol,
+                        max_iters=cap)
+        st, m, prev = o["state"].astype(np.float32), o["mask"].astype(np.uint64), o["contact_key"].astype(np.uint64)
+        sweeps += int(o["max_iters"])
+    dt = time.perf_counter() - t0
+    return {"value": sc.n_bodies * n_steps / dt, "unit": "body-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (double precision, one thread, adaptive sweeps to {tol:g}, cap {cap}) on the first "
+                      f"{n_steps} steps of the same run (contacts begin near step 20); mean "
+                      f"{sweeps / n_steps:.0f} sweeps per step, {dt:.1f} s"}
+
+
 def per_scene_loop(sc, p, args, timed):
     """One world per scene, stepped one after the other (default launch, no graph)."""
     import paper_2403_17261_amd as ovl
@@ -225,7 +355,7 @@ def per_scene_loop(sc, p, args, timed):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["tower", "bowl", "batched"], default="tower")
+    ap.add_argument("--workload", choices=["tower", "bowl", "bowl-lb", "batched"], default="tower")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps first (default 10; batched: 150, so the piles have formed)")
@@ -261,6 +391,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
+        return
+    if args.workload == "bowl-lb":
+        bench_bowl_lb(args)
         return
     if args.workload == "batched":
         if args.warmup is None:

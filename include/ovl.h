@@ -152,9 +152,8 @@ ovl_status ovl_set_partitions(ovl_world* w, const int32_t* owner, int64_t n_bodi
 /* Dynamic load balancing (section 5.4: Alg. 6 with the bridge test of
  * Alg. 7).  enable = 0: every step's worker sets are the halo of the owners
  * (ovl_set_partitions).  enable = 1: the worker sets are carried from step to
- * step; each step first updates them from its new contacts (contacts between
- * two dynamic bodies whose key, as CONTACT_KEY, was not in the previous
- * committed step's list), taken in key order:
+ * step; each step first updates them from its contacts between two dynamic
+ * bodies (as CONTACT_KEY lists them), taken in key order:
  *   - bodies A, B with disjoint sets: the set of smaller load (number of
  *     bodies active in it, summed over its workers; a tie goes to A) is
  *     activated on the other body, and every vertex within `depth` hops of
@@ -166,14 +165,11 @@ ovl_status ovl_set_partitions(ovl_world* w, const int32_t* owner, int64_t n_bodi
  * depth in [0, 64] is the paper's growth depth gamma.  sets (host, n_sets =
  * n_bodies, or NULL) gives the starting sets as local partition bits, each
  * non-empty and inside its scene's partitions; NULL starts every body in its
- * owner only.  prev_keys (host, strictly increasing, n_prev >= 0) are the
- * keys treated as the previous step's contacts; NULL/0 makes every contact of
- * the next step new.  Both are copied.  The sets and keys carried forward are
- * those of the last step that committed; ovl_set_partitions restarts them
- * from the owners.  halo_k is not used while enabled.
+ * owner only (the naive start of section 5.4).  Copied.  The sets carried
+ * forward are those of the last step that committed; ovl_set_partitions
+ * restarts them from the owners.  halo_k is not used while enabled.
  * Errors: INVALID_ARG, OOM, DEVICE. */
-ovl_status ovl_set_load_balance(ovl_world* w, int32_t enable, int32_t depth, const uint64_t* sets, int64_t n_sets,
-                                const uint64_t* prev_keys, int64_t n_prev);
+ovl_status ovl_set_load_balance(ovl_world* w, int32_t enable, int32_t depth, const uint64_t* sets, int64_t n_sets);
 
 /* Run n_steps steps.  Asynchronous on the world's stream when stats is NULL
  * (errors then surface at the next synchronising call); with stats non-NULL

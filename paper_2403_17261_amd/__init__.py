@@ -112,7 +112,7 @@ def lib():
             "ovl_synchronize": (C.c_int, [P]),
             "ovl_read_debug": (C.c_int, [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]),
             "ovl_force_iters": (C.c_int, [P, P, C.c_int32]),
-            "ovl_set_load_balance": (C.c_int, [P, C.c_int32, C.c_int32, P, C.c_int64, P, C.c_int64]),
+            "ovl_set_load_balance": (C.c_int, [P, C.c_int32, C.c_int32, P, C.c_int64]),
             "ovl_last_error": (C.c_char_p, [P]),
             "ovl_get_counters": (C.c_int, [P, C.POINTER(ovl_counters)]),
             "ovl_profile": (C.c_int, [P, C.c_int32]),
@@ -283,16 +283,13 @@ class World:
         self._check(lib().ovl_set_partitions(self.h, _p(o), self.N, _p(pps), len(pps), int(halo_k), int(beta)))
         self.G = int(pps.sum())
 
-    def set_load_balance(self, enable=True, depth=0, sets=None, prev_keys=None):
+    def set_load_balance(self, enable=True, depth=0, sets=None):
         """Dynamic load balancing (section 5.4, Alg. 6-7): carried worker sets
-        updated from each step's new contacts.  sets: u64 [N] local partition
-        bits (None: owners); prev_keys: ascending u64 contact keys taken as
-        the previous step's (None: none)."""
+        updated from each step's contacts.  sets: u64 [N] local partition bits
+        (None: every body in its owner only)."""
         m = None if sets is None else np.ascontiguousarray(sets, np.uint64)
-        k = np.ascontiguousarray(np.zeros(0) if prev_keys is None else prev_keys, np.uint64)
         self._check(lib().ovl_set_load_balance(self.h, int(bool(enable)), int(depth),
-                                               None if m is None else _p(m), 0 if m is None else m.size,
-                                               _p(k) if k.size else None, int(k.size)))
+                                               None if m is None else _p(m), 0 if m is None else m.size))
 
     def step(self, n=1, stats=False, exact=False, allow_not_converged=True):
         if not stats:

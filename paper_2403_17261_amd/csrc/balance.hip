@@ -1,14 +1,17 @@
 // Dynamic load balancing of the worker sets (section 5.4): Alg. 6 over the
-// contacts that are new in this step, with the bridge test of Alg. 7.
+// step's contacts, with the bridge test of Alg. 7.
 //
 // The worker sets W_b (one u64 of local partition bits per body) are carried
-// from the last committed step.  A contact is new when its key is absent from
-// the last committed step's sorted key list; only contacts between two dynamic
-// bodies take part (statics are not vertices of the constraint graph).  The
-// rules are order dependent (every activation changes the loads the next
-// decision reads), so the new contacts of a scene are taken one at a time in
-// key order by one wavefront, while the wavefront's lanes share the work
-// inside a rule: load sums, the bridge test's neighbour union, the growth BFS.
+// from the last committed step.  Every contact of the step between two
+// dynamic bodies is taken in key order (statics are not vertices of the
+// constraint graph).  The rules are order dependent: an activation changes the
+// loads the next decision reads, and any rule changes the sets the next
+// contacts see.  One wavefront per scene therefore walks the scene's contacts
+// with a 64-wide window: every lane tests whether the rule of its contact
+// would change anything in the current state.  Contacts before the first lane
+// that would are no-ops in sequence too (nothing before them changes the
+// state), so the window skips them, applies that one contact with the whole
+// wavefront, and restarts right after it.  The result is the sequential one.
 // Scenes are independent and run as separate workgroups.
 //
 // Readings (the same as stated by the oracle):
@@ -25,52 +28,10 @@ namespace {
 
 constexpr int kLbBS = 64;  // one wavefront per scene
 
-__device__ __forceinline__ uint64_t contact_key(const WP& w, int i) {
-  return ((uint64_t)(uint32_t)w.c_a[i] << 32) | (uint64_t)w.c_bkey[i];
-}
-
-__device__ __forceinline__ bool in_prev(const WP& w, uint64_t key, int n) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (w.lb_prev[mid] < key)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo < n && w.lb_prev[lo] == key;
-}
-
 // worker sets of the last committed step
 __global__ void k_lb_begin(WP w) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < w.N) w.mask[v] = w.lb_mask[v];
-}
-
-// per body: its new contacts (as the first body of the pair), flagged
-__global__ void k_lb_count(WP w) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= w.N) return;
-  int n = 0;
-  if (w.scal[SC_FLAGS] == 0) {
-    const int nprev = w.scal[SC_LB_NPREV];
-    const int c1 = min(w.coff[a + 1], w.Ccap);
-    for (int c = w.coff[a]; c < c1; ++c) {
-      const bool nw = (int)(w.c_bkey[c] >> 1) < w.N && !in_prev(w, contact_key(w, c), nprev);
-      w.lb_flag[c] = nw ? 1 : 0;
-      n += nw ? 1 : 0;
-    }
-  }
-  w.lb_cnt[a] = n;
-}
-
-__global__ void k_lb_fill(WP w) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= w.N || w.lb_cnt[a] == 0) return;
-  int p = w.lb_pos[a];
-  const int c1 = min(w.coff[a + 1], w.Ccap);
-  for (int c = w.coff[a]; c < c1; ++c)
-    if (w.lb_flag[c]) w.lb_new[p++] = c;
 }
 
 // Where a scene's sets, growth queue and visited bits live: LDS for scenes of
@@ -107,8 +68,19 @@ __device__ __forceinline__ void deactivate(const LbMem& L, int* load, uint64_t s
   __syncthreads();
 }
 
-// Alg. 7: the union of the neighbours' worker sets spans more than one worker
-__device__ __forceinline__ bool bridge(const WP& w, const LbMem& L, int b0, int n, int v) {
+// Alg. 7 by one lane: the union of the neighbours' sets spans more than one worker
+__device__ __forceinline__ bool bridge_lane(const WP& w, const LbMem& L, int b0, int n, int v) {
+  uint64_t acc = 0;
+  const int o1 = w.adj_off[b0 + v + 1];
+  for (int k = w.adj_off[b0 + v]; k < o1; ++k) {
+    const int u = w.adj[k] - b0;
+    if (u >= 0 && u < n) acc |= L.m[u];
+  }
+  return __popcll(acc) > 1;
+}
+
+// Alg. 7 by the whole wavefront
+__device__ __forceinline__ bool bridge_wave(const WP& w, const LbMem& L, int b0, int n, int v) {
   const int o0 = w.adj_off[b0 + v], o1 = w.adj_off[b0 + v + 1];
   uint64_t acc = 0;
   for (int k = o0 + lane_id(); k < o1; k += 64) {
@@ -116,6 +88,19 @@ __device__ __forceinline__ bool bridge(const WP& w, const LbMem& L, int b0, int 
     if (u >= 0 && u < n) acc |= L.m[u];
   }
   return __popcll(wave_or(acc)) > 1;
+}
+
+// Would the rule of contact (a, b) change any set in the current state?  (One
+// lane.)  The first rule always adds workers; the bridge rules remove at least
+// one; the last rule removes workers exactly when the common set has several.
+__device__ __forceinline__ bool rule_changes(const WP& w, const LbMem& L, int b0, int n, int a, int b) {
+  const uint64_t WA = L.m[a], WB = L.m[b];
+  if ((WA & WB) == 0ull) return true;
+  const int pa = __popcll(WA), pb = __popcll(WB);
+  if (pa > 1 && pb == 1 && !bridge_lane(w, L, b0, n, a)) return true;
+  if (pb > 1 && pa == 1 && !bridge_lane(w, L, b0, n, b)) return true;
+  if (WA == WB) return pa > 1;
+  return false;
 }
 
 // Growth of the first rule: every vertex within `depth` hops of root (root
@@ -157,6 +142,48 @@ __device__ void grow(const WP& w, const LbMem& L, int* load, int* tail, int b0, 
   __syncthreads();
 }
 
+// Alg. 6 for one contact, by the whole wavefront (a, b uniform)
+__device__ void apply_rule(const WP& w, const LbMem& L, int* load, int* tail, int b0, int n, int a, int b) {
+  const int lane = lane_id();
+  const uint64_t WA = L.m[a], WB = L.m[b];
+  if ((WA & WB) == 0ull) {
+    // Figure 9 (i), (ii): the lighter side becomes aware of the other body
+    const long long la = set_load(WA, load[lane]), lb = set_load(WB, load[lane]);
+    int root;
+    if (la <= lb) {
+      activate(L, load, WA, b);
+      root = b;
+    } else {
+      activate(L, load, WB, a);
+      root = a;
+    }
+    grow(w, L, load, tail, b0, n, root, WA | WB, w.lb_depth);
+  } else if (__popcll(WA) > 1 && __popcll(WB) == 1 && !bridge_wave(w, L, b0, n, a)) {
+    deactivate(L, load, WA & ~WB, a);  // Figure 9 (iii); (iv) is the bridge case
+  } else if (__popcll(WB) > 1 && __popcll(WA) == 1 && !bridge_wave(w, L, b0, n, b)) {
+    deactivate(L, load, WB & ~WA, b);
+  } else if (WA == WB) {
+    // Figure 9 (v): both keep only the least loaded of their workers
+    long long key = ((WA >> lane) & 1ull) ? (((long long)load[lane] << 6) | lane) : 0x7fffffffffffffffll;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const long long o = __shfl_xor(key, d, 64);
+      key = o < key ? o : key;
+    }
+    const uint64_t keep = 1ull << (key & 63);
+    deactivate(L, load, WA & ~keep, a);
+    deactivate(L, load, WB & ~keep, b);
+  }
+}
+
+// (local a, local b) of contact i of the scene, or (-1, -1) past the end or for a static
+__device__ __forceinline__ int2 contact_pair(const WP& w, int i, int c1, int b0) {
+  if (i >= c1) return make_int2(-1, -1);
+  const int bc = (int)(w.c_bkey[i] >> 1);
+  if (bc >= w.N) return make_int2(-1, -1);
+  return make_int2(w.c_a[i] - b0, bc - b0);
+}
+
 template <bool kLds>
 __global__ __launch_bounds__(kLbBS) void k_load_balance(WP w) {
   extern __shared__ uint64_t lds_m[];
@@ -166,8 +193,8 @@ __global__ __launch_bounds__(kLbBS) void k_load_balance(WP w) {
   if (w.scal[SC_FLAGS] != 0) return;
   const int b0 = w.s_body_off[s], b1 = w.s_body_off[s + 1], n = b1 - b0;
   if (kLds != (n <= kLbLdsCap)) return;
-  const int q0 = w.lb_pos[b0], q1 = w.lb_pos[b1];
-  if (q0 >= q1) return;  // no new contact: the carried sets stand
+  const int c0 = w.coff[b0], c1 = w.coff[b1];
+  if (c0 >= c1) return;  // no contact: the carried sets stand
   const int np = w.s_part_base[s + 1] - w.s_part_base[s];
   LbMem L;
   if (kLds) {
@@ -205,60 +232,40 @@ __global__ __launch_bounds__(kLbBS) void k_load_balance(WP w) {
   load[lane] = my_load;
   __syncthreads();
 
-  for (int qb = q0; qb < q1; qb += 64) {
-    int A = -1, B = -1;
-    if (qb + lane < q1) {
-      const int c = w.lb_new[qb + lane];
-      A = w.c_a[c] - b0;
-      B = (int)(w.c_bkey[c] >> 1) - b0;
+  // the window: lane l holds contacts cb + l (x0) and cb + 64 + l (x1)
+  int cb = c0;
+  int2 x0 = contact_pair(w, cb + lane, c1, b0);
+  int2 x1 = contact_pair(w, cb + 64 + lane, c1, b0);
+  int c = c0;
+  while (c < c1) {
+    while (c >= cb + 64) {
+      x0 = x1;
+      cb += 64;
+      x1 = contact_pair(w, cb + 64 + lane, c1, b0);
     }
-    const int cnt = min(64, q1 - qb);
-    for (int j = 0; j < cnt; ++j) {
-      const int a = __shfl(A, j, 64), b = __shfl(B, j, 64);
-      if (a < 0 || a >= n || b < 0 || b >= n) continue;
-      const uint64_t WA = L.m[a], WB = L.m[b];
-      if ((WA & WB) == 0ull) {
-        // Figure 9 (i), (ii): the lighter side becomes aware of the other body
-        const long long la = set_load(WA, load[lane]), lb = set_load(WB, load[lane]);
-        int root;
-        if (la <= lb) {
-          activate(L, load, WA, b);
-          root = b;
-        } else {
-          activate(L, load, WB, a);
-          root = a;
-        }
-        grow(w, L, load, &tail, b0, n, root, WA | WB, w.lb_depth);
-      } else if (__popcll(WA) > 1 && __popcll(WB) == 1 && !bridge(w, L, b0, n, a)) {
-        deactivate(L, load, WA & ~WB, a);  // Figure 9 (iii); (iv) is the bridge case
-      } else if (__popcll(WB) > 1 && __popcll(WA) == 1 && !bridge(w, L, b0, n, b)) {
-        deactivate(L, load, WB & ~WA, b);
-      } else if (WA == WB) {
-        // Figure 9 (v): both keep only the least loaded of their workers
-        long long key = ((WA >> lane) & 1ull) ? (((long long)load[lane] << 6) | lane) : 0x7fffffffffffffffll;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          const long long o = __shfl_xor(key, d, 64);
-          key = o < key ? o : key;
-        }
-        const uint64_t keep = 1ull << (key & 63);
-        deactivate(L, load, WA & ~keep, a);
-        deactivate(L, load, WB & ~keep, b);
-      }
+    const int src = c - cb + lane;  // 0..127
+    const int sl = src & 63;
+    const int a0 = __shfl(x0.x, sl, 64), bb0 = __shfl(x0.y, sl, 64);
+    const int a1 = __shfl(x1.x, sl, 64), bb1 = __shfl(x1.y, sl, 64);
+    const int a = src < 64 ? a0 : a1, b = src < 64 ? bb0 : bb1;
+    const bool live = a >= 0 && a < n && b >= 0 && b < n;
+    const uint64_t fire = __ballot(live && rule_changes(w, L, b0, n, a, b));
+    if (fire == 0ull) {
+      c += 64;
+      continue;
     }
+    const int j = __builtin_ctzll(fire);
+    apply_rule(w, L, load, &tail, b0, n, __shfl(a, j, 64), __shfl(b, j, 64));
+    c += j + 1;
   }
   if (kLds)
     for (int i = lane; i < n; i += 64) w.mask[b0 + i] = L.m[i];
 }
 
-// after a committed step: its sets and sorted contact keys are carried
+// after a committed step: its sets are carried
 __global__ void k_lb_commit(WP w) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w.scal[SC_FLAGS] != 0) return;
-  const int nc = w.scal[SC_NCONTACT];
-  if (i < w.N) w.lb_mask[i] = w.mask[i];
-  if (i < nc) w.lb_prev[i] = contact_key(w, i);
-  if (i == 0) w.scal[SC_LB_NPREV] = nc;
+  if (i < w.N && w.scal[SC_FLAGS] == 0) w.lb_mask[i] = w.mask[i];
 }
 
 }  // namespace
@@ -270,24 +277,17 @@ hipError_t lb_set_attributes() {
                              (int)lb_lds_bytes(kLbLdsCap));
 }
 
-hipError_t launch_balance(const WP& w, int32_t* sc, hipStream_t s) {
-  hipError_t e;
+hipError_t launch_balance(const WP& w, hipStream_t s) {
   if (w.N <= 0) return hipSuccess;
-  const int nb = nblocks(w.N, kBlock);
-  k_lb_begin<<<nb, kBlock, 0, s>>>(w);
-  k_lb_count<<<nb, kBlock, 0, s>>>(w);
-  if ((e = hipGetLastError())) return e;
-  if ((e = scan_excl(w.lb_cnt, w.lb_pos, w.N, nullptr, sc, s))) return e;
-  k_lb_fill<<<nb, kBlock, 0, s>>>(w);
+  k_lb_begin<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
   if (w.lb_lds_max > 0) k_load_balance<true><<<w.S, kLbBS, lb_lds_bytes(w.lb_lds_max), s>>>(w);
   if (w.lb_big) k_load_balance<false><<<w.S, kLbBS, 0, s>>>(w);
   return hipGetLastError();
 }
 
 hipError_t launch_balance_commit(const WP& w, hipStream_t s) {
-  const int n = w.N > w.Ccap ? w.N : w.Ccap;
-  if (n <= 0) return hipSuccess;
-  k_lb_commit<<<nblocks(n, kBlock), kBlock, 0, s>>>(w);
+  if (w.N <= 0) return hipSuccess;
+  k_lb_commit<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
   return hipGetLastError();
 }
 

@@ -384,8 +384,8 @@ hipError_t launch_graph(const WP& w, int32_t* sc, hipStream_t s) {
     if (w.Ccap > 0) k_adj_contacts<<<ncb, kBlock, 0, s>>>(w);
     k_adj_sort<<<nb, kBlock, 0, s>>>(w);
     if (w.lb_on) {
-      // worker sets carried from the last step, updated from the new contacts
-      if ((e = launch_balance(w, sc, s))) return e;
+      // worker sets carried from the last step, updated from this step's contacts
+      if ((e = launch_balance(w, s))) return e;
     } else {
       // overlap masks: k rounds of neighbour OR
       k_mask_init<<<nb, kBlock, 0, s>>>(w);

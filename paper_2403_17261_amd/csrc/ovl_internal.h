@@ -38,7 +38,6 @@ enum Scal {
   SC_NJCOPY,         // joint copies
   SC_NCCOPY,         // contact copies
   SC_NOVERLAP,       // bodies in >= 2 partitions
-  SC_LB_NPREV,       // contact keys carried for the load balancing (last committed step)
   SC_COUNT = 16
 };
 
@@ -189,16 +188,11 @@ struct WP {
                                 //      2 algorithmic bytes of the sweeps, 3 sweeps summed over partitions,
                                 //      4 committed steps
   // dynamic load balancing: worker sets carried from step to step
-  int32_t lb_on;                // 1: sets carried and updated from the new contacts; 0: k-hop halo
+  int32_t lb_on;                // 1: sets carried and updated from each step's contacts; 0: k-hop halo
   int32_t lb_depth;             // growth depth of the inter-worker rule
   int32_t lb_lds_max;           // largest scene of at most kLbLdsCap bodies (LDS layout size), 0 if none
   int32_t lb_big;               // 1: some scene has more than kLbLdsCap bodies
   uint64_t* lb_mask;            // [N] sets of the last committed step
-  uint64_t* lb_prev;            // [>= Ccap] contact keys of the last committed step, ascending
-  int32_t* lb_cnt;              // [N+1] new contacts per first body
-  int32_t* lb_pos;              // [N+1] exclusive prefix of lb_cnt
-  int32_t* lb_flag;             // [Ccap] 1: the contact is new and joins two dynamic bodies
-  int32_t* lb_new;              // [Ccap] new contacts in key order
   int32_t* lb_queue;            // [N] growth BFS queue of scenes kept in global memory
   uint32_t* lb_visit;           // [N/32+1] growth BFS visited bits of scenes kept in global memory
   // scalars
@@ -240,7 +234,7 @@ constexpr int64_t kBytesStatic = 164;
 constexpr int64_t kBytesJoint = 192;
 hipError_t pgs_set_attributes();
 // dynamic load balancing (between the graph and the replica table; commit after the blend)
-hipError_t launch_balance(const WP& w, int32_t* scan_scratch, hipStream_t s);
+hipError_t launch_balance(const WP& w, hipStream_t s);
 hipError_t launch_balance_commit(const WP& w, hipStream_t s);
 hipError_t lb_set_attributes();
 hipError_t launch_mlp_world(const WP& w, hipStream_t s);

@@ -52,11 +52,8 @@ struct ovl_world {
   int64_t pgs_launches = 0;
   uint16_t* mlp_wb = nullptr;
   float* mlp_bias = nullptr;
-  // dynamic load balancing: per-body buffers (allocated at the first enable) and
-  // the carried contact keys, whose capacity follows the contact capacity
+  // dynamic load balancing: per-body buffers (allocated at the first enable)
   std::vector<void*> lb_allocs;
-  void* lb_prev_buf = nullptr;
-  int32_t lb_cap = 0;
 
   hipEvent_t take_event() {
     if (!ev_pool.empty()) {
@@ -125,7 +122,6 @@ struct ovl_world {
     free_group(part_allocs);
     free_group(cap_allocs);
     free_group(lb_allocs);
-    raw_free(lb_prev_buf);
     free_group(static_allocs);
   }
 
@@ -173,30 +169,7 @@ struct ovl_world {
     w.wc_key = alloc<uint64_t>(g, Mcap, ok);
     w.wc_val = alloc<float>(g, (size_t)4 * Mcap, ok);
     w.mc_blk[2] = alloc<int32_t>(g, (size_t)(nblocks(Ccap, 256) + 1) * 64, ok);
-    w.lb_flag = alloc<int32_t>(g, Ccap, ok);
-    w.lb_new = alloc<int32_t>(g, Ccap, ok);
-    return ok && (lb_prev_buf == nullptr || lb_reserve(Ccap));
-  }
-
-  // Carried contact keys: capacity >= n, the first lb_cap keys kept on growth.
-  bool lb_reserve(int64_t n) {
-    if (lb_prev_buf && n <= lb_cap) return true;
-    const int64_t cap = std::max<int64_t>({n, (int64_t)wp.Ccap, 1024});
-    void* nb = raw_alloc((size_t)cap * sizeof(uint64_t));
-    if (!nb) return false;
-    if (lb_prev_buf) {
-      if (hipMemcpyAsync(nb, lb_prev_buf, (size_t)lb_cap * sizeof(uint64_t), hipMemcpyDeviceToDevice, stream) !=
-              hipSuccess ||
-          hipStreamSynchronize(stream) != hipSuccess) {
-        raw_free(nb);
-        return false;
-      }
-      raw_free(lb_prev_buf);
-    }
-    lb_prev_buf = nb;
-    lb_cap = (int32_t)cap;
-    wp.lb_prev = (uint64_t*)nb;
-    return true;
+    return ok;
   }
 
   bool lb_alloc() {
@@ -204,22 +177,19 @@ struct ovl_world {
     bool ok = true;
     const size_t Np = std::max(N, 1);
     wp.lb_mask = alloc<uint64_t>(lb_allocs, Np, ok);
-    wp.lb_cnt = alloc<int32_t>(lb_allocs, Np + 1, ok);
-    wp.lb_pos = alloc<int32_t>(lb_allocs, Np + 1, ok);
     wp.lb_queue = alloc<int32_t>(lb_allocs, Np, ok);
     wp.lb_visit = alloc<uint32_t>(lb_allocs, Np / 32 + 1, ok);
     if (ok) ok = hipMemsetAsync(wp.lb_visit, 0, (Np / 32 + 1) * sizeof(uint32_t), stream) == hipSuccess &&
                  hipStreamSynchronize(stream) == hipSuccess;
-    if (ok) ok = lb_reserve(wp.Ccap);
     if (!ok) free_group(lb_allocs);
     return ok;
   }
 
-  // carried sets = owners' singletons (the naive start of section 5.4), no carried keys
+  // carried sets = owners' singletons (the naive start of section 5.4)
   bool lb_reset_to_owners(const std::vector<int32_t>& local) {
     std::vector<uint64_t> m(std::max(N, 1), 0);
     for (int i = 0; i < N; ++i) m[i] = 1ull << local[i];
-    return upload(wp.lb_mask, m.data(), (size_t)N * sizeof(uint64_t)) && write_scal(SC_LB_NPREV, 0);
+    return upload(wp.lb_mask, m.data(), (size_t)N * sizeof(uint64_t)) && hipStreamSynchronize(stream) == hipSuccess;
   }
 
   bool alloc_parts(int32_t G_) {
@@ -723,7 +693,7 @@ ovl_status ovl_set_partitions(ovl_world* w, const int32_t* owner, int64_t n_bodi
 }
 
 ovl_status ovl_set_load_balance(ovl_world* w, int32_t enable, int32_t depth, const uint64_t* sets,
-                                int64_t n_sets, const uint64_t* prev_keys, int64_t n_prev) {
+                                int64_t n_sets) {
   if (!w) return OVL_ERR_INVALID_ARG;
   if (enable != 0 && enable != 1) return w->fail(OVL_ERR_INVALID_ARG, "enable must be 0 or 1");
   if (!enable) {
@@ -732,22 +702,16 @@ ovl_status ovl_set_load_balance(ovl_world* w, int32_t enable, int32_t depth, con
   }
   if (depth < 0 || depth > 64) return w->fail(OVL_ERR_INVALID_ARG, "depth must be in [0,64]");
   if (sets && n_sets != w->N) return w->fail(OVL_ERR_INVALID_ARG, "sets must have n_bodies entries");
-  if (n_prev < 0 || (n_prev > 0 && !prev_keys)) return w->fail(OVL_ERR_INVALID_ARG, "bad prev_keys");
-  if (n_prev > (int64_t)1 << 30) return w->fail(OVL_ERR_INVALID_ARG, "too many prev_keys");
   if (sets)
     for (int s = 0; s < w->S; ++s)
       for (int i = w->body_off[s]; i < w->body_off[s + 1]; ++i)
         if (sets[i] == 0 || (w->pps[s] < 64 && (sets[i] >> w->pps[s]) != 0))
           return w->fail(OVL_ERR_INVALID_ARG, "set of body " + std::to_string(i) +
                                                   " is empty or names a partition outside its scene");
-  for (int64_t i = 1; i < n_prev; ++i)
-    if (prev_keys[i] <= prev_keys[i - 1])
-      return w->fail(OVL_ERR_INVALID_ARG, "prev_keys must be strictly increasing");
   if (hipStreamSynchronize(w->stream) != hipSuccess) return w->fail(OVL_ERR_DEVICE, "sync failed");
-  if (!w->lb_alloc() || !w->lb_reserve(n_prev)) return w->fail(OVL_ERR_OOM, "load-balancing buffers");
-  bool ok = sets ? w->upload(w->wp.lb_mask, sets, (size_t)w->N * sizeof(uint64_t)) : w->lb_reset_to_owners(w->owner_local);
-  ok = ok && w->upload(w->wp.lb_prev, prev_keys, (size_t)n_prev * sizeof(uint64_t)) &&
-       w->write_scal(SC_LB_NPREV, (int32_t)n_prev);
+  if (!w->lb_alloc()) return w->fail(OVL_ERR_OOM, "load-balancing buffers");
+  bool ok = sets ? w->upload(w->wp.lb_mask, sets, (size_t)w->N * sizeof(uint64_t))
+                 : w->lb_reset_to_owners(w->owner_local);
   if (!ok || hipStreamSynchronize(w->stream) != hipSuccess) return w->fail(OVL_ERR_DEVICE, "upload failed");
   w->wp.lb_on = 1;
   w->wp.lb_depth = depth;

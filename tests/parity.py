@@ -60,8 +60,8 @@ def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, fo
                  check_lambda0=True, lb=None):
     """One GPU step from the world's current state against one oracle step from the same inputs.
 
-    lb: None (k-hop halo sets), or dict(sets=, prev=, depth=) giving the carried
-    worker sets and previous contact keys the world was given for this step."""
+    lb: None (k-hop halo sets), or dict(sets=, depth=) giving the carried worker
+    sets the world holds for this step and the growth depth."""
     halo_k = sc.halo_k if halo_k is None else halo_k
     beta = sc.beta if beta is None else beta
     owner = sc.owner if owner is None else owner
@@ -77,8 +77,7 @@ def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, fo
     gs = w.read_state()
     kw = oracle_kwargs(sc, params, halo_k, beta)
     if lb is not None:
-        kw.update(lb_masks=np.asarray(lb["sets"], np.uint64), lb_prev_keys=np.asarray(lb["prev"], np.uint64),
-                  lb_depth=int(lb["depth"]))
+        kw.update(lb_masks=np.asarray(lb["sets"], np.uint64), lb_depth=int(lb["depth"]))
     o = oracle.step(sc, state=s0, owner=owner, parts_per_scene=pps, cache=cache,
                     forced_iters=forced if forced is not None else None, **kw)
     log(f"  {label} contacts={len(o['contact_key'])} copies={len(o['copy_key'])} replicas={len(o['rep_body'])} "

@@ -114,7 +114,7 @@ def test_null_world_is_rejected():
     assert L.ovl_step(None, 1, None, 0) == ovl.ERR_INVALID_ARG
     assert L.ovl_set_partitions(None, None, 0, None, 0, 1, 1) == ovl.ERR_INVALID_ARG
     assert L.ovl_read_state(None, None, 0, 0) == ovl.ERR_INVALID_ARG
-    assert L.ovl_set_load_balance(None, 1, 0, None, 0, None, 0) == ovl.ERR_INVALID_ARG
+    assert L.ovl_set_load_balance(None, 1, 0, None, 0) == ovl.ERR_INVALID_ARG
     L.ovl_destroy_world(None)
 
 

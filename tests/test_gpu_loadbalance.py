@@ -1,16 +1,17 @@
 """GPU parity of the dynamic load balancing (section 5.4, Alg. 6 with the
 bridge test of Alg. 7) against the oracle.
 
-The carried worker sets and the previous step's contact keys are inputs of a
-step; every case hands the same ones to both sides and compares the sets the
-step produces bit for bit, then the rest of the step (replica tables, weights,
-velocities) as every other parity test does.  Start states, sets and keys come
-from oracle runs, except in the trajectory test, which compares one step
-after a GPU run from that run's own state.
+The carried worker sets are an input of a step; every case hands the same
+sets to both sides and compares the sets the step produces bit for bit, then
+the rest of the step (replica tables, weights, velocities) as every other
+parity test does.  Start states and sets come from oracle runs, except in the
+trajectory test, which compares one step after a GPU run from that run's own
+state and sets.
 
-Cases: the Figure 9 scenarios on hand-placed spheres; a settling bowl from the
-naive start at growth depths 0 and 2 (scenes kept in LDS); a bowl larger than
-the LDS limit (scene kept in global memory); several scenes at once; the
+Cases: the Figure 9 scenarios on hand-placed spheres, including the chain at
+growth depths 0 to 3 and an isolated collision over two steps; a settling bowl
+from the naive start at depths 0 and 2 (scenes kept in LDS); a bowl larger
+than the LDS limit (scene kept in global memory); several scenes at once; the
 graph-replayed step against the eager one.
 """
 import numpy as np
@@ -28,11 +29,6 @@ STEP = 0.98
 FAR = [100.0, 110.0, 120.0, 130.0, 140.0, 150.0]
 
 
-def _key(a, b):
-    a, b = min(a, b), max(a, b)
-    return (a << 32) | (b << 1)
-
-
 def _world(sc, **pkw):
     p = ovl.make_params(dt=sc.dt, max_iters=sc.iters, **pkw)
     w = ovl.World(sc, p)
@@ -46,61 +42,71 @@ def _line(xs, owner, n_parts):
 
 
 FIG9 = [
-    # (label, xs, owner, n_parts, sets, previous pairs, depth)
-    ("i lighter side", [0.0, STEP] + FAR[:2], [0, 1, 0, 0], 2, [1, 2, 1, 1], [], 0),
-    ("i tie", [0.0, STEP], [0, 1], 2, [1, 2], [], 0),
-    ("ii depth 2", [i * STEP for i in range(5)], [0, 1, 1, 1, 1], 2, [1, 2, 2, 2, 2],
-     [(1, 2), (2, 3), (3, 4)], 2),
-    ("iii", [0.0, STEP] + FAR[:1], [0, 0, 1], 2, [3, 1, 2], [], 0),
-    ("iii mirror", [0.0, STEP] + FAR[:1], [0, 0, 1], 2, [1, 3, 2], [], 0),
-    ("iv bridge", [0.0, STEP, 2 * STEP], [0, 0, 1], 2, [1, 3, 2], [(1, 2)], 0),
-    ("v", [0.0, STEP] + FAR[:4], [0, 0, 0, 0, 0, 1], 2, [3, 3, 1, 1, 1, 2], [], 0),
-    ("v three workers", [0.0, STEP] + FAR[:3], [1, 1, 0, 0, 0], 3, [6, 6, 1, 1, 1], [], 0),
-    ("key order", [0.0, 20.0, STEP, 20.0 + STEP], [0, 0, 1, 1], 2, [1, 1, 2, 2], [], 0),
-    ("set load is a sum", [0.0, STEP] + FAR[:3], [0, 2, 0, 1, 2], 3, [3, 4, 1, 2, 4], [], 0),
-    ("old contact", [0.0, STEP], [0, 1], 2, [1, 2], [(0, 1)], 0),
+    # (label, xs, owner, n_parts, sets, depth)
+    ("i lighter side", [0.0, STEP] + FAR[:2], [0, 1, 0, 0], 2, [1, 2, 1, 1], 0),
+    ("i tie", [0.0, STEP], [0, 1], 2, [1, 2], 0),
+    ("ii depth 0", [i * STEP for i in range(5)], [0, 1, 1, 1, 1], 2, [1, 2, 2, 2, 2], 0),
+    ("ii depth 1", [i * STEP for i in range(5)], [0, 1, 1, 1, 1], 2, [1, 2, 2, 2, 2], 1),
+    ("ii depth 2", [i * STEP for i in range(5)], [0, 1, 1, 1, 1], 2, [1, 2, 2, 2, 2], 2),
+    ("ii depth 3", [i * STEP for i in range(5)], [0, 1, 1, 1, 1], 2, [1, 2, 2, 2, 2], 3),
+    ("iii", [0.0, STEP] + FAR[:1], [0, 0, 1], 2, [3, 1, 2], 0),
+    ("iii mirror", [0.0, STEP] + FAR[:1], [0, 0, 1], 2, [1, 3, 2], 0),
+    ("iv bridge", [0.0, STEP, 2 * STEP], [0, 0, 1], 2, [1, 3, 2], 0),
+    ("v", [0.0, STEP] + FAR[:4], [0, 0, 0, 0, 0, 1], 2, [3, 3, 1, 1, 1, 2], 0),
+    ("v three workers", [0.0, STEP] + FAR[:3], [1, 1, 0, 0, 0], 3, [6, 6, 1, 1, 1], 0),
+    ("key order", [0.0, 20.0, STEP, 20.0 + STEP], [0, 0, 1, 1], 2, [1, 1, 2, 2], 0),
+    ("set load is a sum", [0.0, STEP] + FAR[:3], [0, 2, 0, 1, 2], 3, [3, 4, 1, 2, 4], 0),
 ]
 
 
 @pytest.mark.parametrize("case", FIG9, ids=[c[0] for c in FIG9])
 def test_figure9_scenarios(case):
-    label, xs, owner, n_parts, sets, prev, depth = case
+    label, xs, owner, n_parts, sets, depth = case
     sc = _line(xs, owner, n_parts)
     w, p = _world(sc)
-    keys = np.array(sorted(_key(a, b) for a, b in prev), np.uint64)
     sets = np.asarray(sets, np.uint64)
-    w.set_load_balance(True, depth, sets=sets, prev_keys=keys)
-    _, o = compare_step(sc, w, p, label=f"fig 9 {label}", lb=dict(sets=sets, prev=keys, depth=depth))
+    w.set_load_balance(True, depth, sets=sets)
+    _, o = compare_step(sc, w, p, label=f"fig 9 {label}", lb=dict(sets=sets, depth=depth))
     log(f"  sets {sets.tolist()} -> {o['mask'].tolist()}")
 
 
+def test_isolated_collision_over_two_steps():
+    """(i) in the first step, (iii) in the second: the library carries its own sets."""
+    sc = _line([0.0, STEP], [0, 1], 2)
+    w, p = _world(sc)
+    w.set_load_balance(True, 0)
+    _, o1 = compare_step(sc, w, p, label="(i)", lb=dict(sets=[1, 2], depth=0))
+    assert o1["mask"].tolist() == [1, 3]
+    _, o2 = compare_step(sc, w, p, label="(iii)", lb=dict(sets=[1, 3], depth=0))
+    assert o2["mask"].tolist() == [1, 1]
+
+
 def _oracle_start(sc, steps, depth):
-    """State, sets and keys after `steps` oracle steps from the naive start."""
+    """State and sets after `steps` oracle steps from the naive start."""
     st, out, _ = oracle.run_lb(sc, steps, depth, dt=sc.dt, max_iters=sc.iters, beta=sc.beta)
-    return st, out["mask"].astype(np.uint64), out["contact_key"].astype(np.uint64), out
+    return st, out["mask"].astype(np.uint64), out
 
 
 @pytest.mark.parametrize("depth", [0, 2])
 def test_bowl_from_oracle_state(depth):
     sc = scenes.bowl_naive(1200, 3, 5, squeeze=0.35)
-    st, sets, keys, o_prev = _oracle_start(sc, 4, depth)
+    st, sets, o_prev = _oracle_start(sc, 4, depth)
     w, p = _world(sc)
     w.write_state(st, keep_cache=False)
     w.write_cache(o_prev)
-    w.set_load_balance(True, depth, sets=sets, prev_keys=keys)
-    stats, o = compare_step(sc, w, p, label=f"bowl 1200 depth {depth}", lb=dict(sets=sets, prev=keys, depth=depth))
+    w.set_load_balance(True, depth, sets=sets)
+    _, o = compare_step(sc, w, p, label=f"bowl 1200 depth {depth}", lb=dict(sets=sets, depth=depth))
     changed = int((o["mask"] != sets).sum())
     log(f"  sets changed on {changed} bodies, overlap {o['n_overlap']}")
     assert changed > 0
 
 
 def test_bowl_naive_start_first_step():
-    """Every contact of the first step is new (no carried keys)."""
     sc = scenes.bowl_naive(1200, 4, 6, squeeze=0.35)
     w, p = _world(sc)
     sets = oracle.initial_masks(sc)
     w.set_load_balance(True, 1)
-    _, o = compare_step(sc, w, p, label="bowl naive first step", lb=dict(sets=sets, prev=[], depth=1))
+    _, o = compare_step(sc, w, p, label="bowl naive first step", lb=dict(sets=sets, depth=1))
     assert int((o["mask"] != sets).sum()) > 0
 
 
@@ -110,12 +116,12 @@ def test_scene_beyond_lds_limit():
     warm-start cache written beforehand must survive that."""
     sc = scenes.bowl_naive(13000, 5, 7, squeeze=0.35)
     assert sc.n_bodies > 12288
-    st, sets, keys, o_prev = _oracle_start(sc, 2, 1)
+    st, sets, o_prev = _oracle_start(sc, 2, 1)
     w, p = _world(sc)
     w.write_state(st, keep_cache=False)
     w.write_cache(o_prev)
-    w.set_load_balance(True, 1, sets=sets, prev_keys=keys)
-    _, o = compare_step(sc, w, p, label="bowl 13000 (global memory)", lb=dict(sets=sets, prev=keys, depth=1))
+    w.set_load_balance(True, 1, sets=sets)
+    _, o = compare_step(sc, w, p, label="bowl 13000 (global memory)", lb=dict(sets=sets, depth=1))
     assert int((o["mask"] != sets).sum()) > 0
 
 
@@ -125,18 +131,14 @@ def test_several_scenes():
     w, p = _world(sc)
     sets = oracle.initial_masks(sc)
     w.set_load_balance(True, 0)
-    _, o = compare_step(sc, w, p, label="three bowls", lb=dict(sets=sets, prev=[], depth=0))
-    sets = o["mask"].astype(np.uint64)
-    keys = o["contact_key"].astype(np.uint64)
-    w.step(1)   # the sets and keys the library carries forward are its own from here
-    g_sets = w.debug("mask").astype(np.uint64)
-    g_keys = w.debug("contact_key").astype(np.uint64)
-    _, o2 = compare_step(sc, w, p, label="three bowls, carried", lb=dict(sets=g_sets, prev=g_keys, depth=0))
+    _, o = compare_step(sc, w, p, label="three bowls", lb=dict(sets=sets, depth=0))
+    w.step(1)   # the sets the library carries forward are its own from here
+    _, o2 = compare_step(sc, w, p, label="three bowls, carried", lb=dict(sets=w.debug("mask"), depth=0))
 
 
 def test_trajectory_and_graph_replay():
     """60 steps from the naive start, eager and graph-replayed: the same bits;
-    then one step against the oracle from the run's state, sets and keys."""
+    then one step against the oracle from the run's state and sets."""
     sc = scenes.bowl_naive(1500, 6, 7, squeeze=0.35)
     out = []
     for graph in (0, 1):
@@ -147,10 +149,10 @@ def test_trajectory_and_graph_replay():
         w.set_load_balance(True, 0)
         for _ in range(3):
             w.step(20)
-        out.append((w.read_state(), w.debug("mask").astype(np.uint64), w.debug("contact_key").astype(np.uint64), w))
+        out.append((w.read_state(), w.debug("mask").astype(np.uint64), w))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
-    st, sets, keys, w = out[0]
+    st, sets, w = out[0]
     assert (sets != 0).all()
     load = [int(((sets >> np.uint64(b)) & np.uint64(1)).sum()) for b in range(7)]
     log(f"  bodies per worker after 60 steps {load}")
-    _, o = compare_step(sc, w, p, label="bowl 1500 t=61", lb=dict(sets=sets, prev=keys, depth=0))
+    compare_step(sc, w, p, label="bowl 1500 t=61", lb=dict(sets=sets, depth=0))
