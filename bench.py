@@ -236,9 +236,10 @@ def bench_bowl_lb(args):
     w, on = timed_run(True)
     # per-worker distributions (Figures 13 and 14): the same trajectory again, sampled every 10 steps
     restart(w, True)
-    bodies, contacts, overlap = [], [], []
+    bodies, contacts, overlap, changes = [], [], [], []
     for t in range(0, steps, 10):
-        w.step(10)
+        w.step(9)
+        changes.append(int(w.step(1, stats=True)["n_lb_changes"]))
         ro = w.debug("part_rep_off").astype(np.int64)
         co = w.debug("part_copy_off").astype(np.int64)
         bodies.append(np.diff(ro))
@@ -278,6 +279,7 @@ def bench_bowl_lb(args):
             "max_over_mean_bodies_second_half": imbalance(bodies[half:]),
             "max_over_mean_contacts_second_half": imbalance(contacts[half:]),
             "overlap_bodies_last": overlap[-1],
+            "rule_changes_per_step_second_half": float(np.mean(changes[half:])),
             "without_balancing": {"ms_per_step": off["ms_per_step"], "body_steps_per_s": off["value"],
                                   "sweeps_per_step": round(off["sweeps_mean"], 2),
                                   "note": "same owners, 1-hop halo of the naive division every step"},

@@ -121,6 +121,7 @@ typedef struct {
   int64_t iters_total;     /* total over the call's steps of the largest sweep count */
   float resid_sweep;       /* largest last-sweep residual max |A_rr dlambda| over partitions (m/s) */
   float resid_exact;       /* natural-map residual of the final iterate (computed when requested) */
+  int64_t n_lb_changes;    /* contacts whose load-balancing rule changed a worker set (last step) */
 } ovl_step_stats;
 
 /* Create a world from a scene description.  Every body starts in partition 0

@@ -69,7 +69,7 @@ class ovl_step_stats(C.Structure):
     _fields_ = [("n_contacts", C.c_int64), ("n_copies", C.c_int64), ("n_replicas", C.c_int64),
                 ("n_overlap", C.c_int64), ("max_colours", C.c_int32), ("max_iters", C.c_int32),
                 ("n_unconverged", C.c_int32), ("steps", C.c_int32), ("iters_total", C.c_int64),
-                ("resid_sweep", C.c_float), ("resid_exact", C.c_float)]
+                ("resid_sweep", C.c_float), ("resid_exact", C.c_float), ("n_lb_changes", C.c_int64)]
 
 
 class ovl_counters(C.Structure):

@@ -346,7 +346,10 @@ __global__ __launch_bounds__(1024) void k_check_copies(WP w) {
 }
 
 __global__ void k_zero_scal(WP w) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) w.scal[SC_NOVERLAP] = 0;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    w.scal[SC_NOVERLAP] = 0;
+    w.scal[SC_LB_CHANGES] = 0;
+  }
 }
 
 template <class I>

@@ -38,6 +38,7 @@ enum Scal {
   SC_NJCOPY,         // joint copies
   SC_NCCOPY,         // contact copies
   SC_NOVERLAP,       // bodies in >= 2 partitions
+  SC_LB_CHANGES,     // contacts whose load-balancing rule changed a worker set
   SC_COUNT = 16
 };
 
@@ -193,8 +194,9 @@ struct WP {
   int32_t lb_lds_max;           // largest scene of at most kLbLdsCap bodies (LDS layout size), 0 if none
   int32_t lb_big;               // 1: some scene has more than kLbLdsCap bodies
   uint64_t* lb_mask;            // [N] sets of the last committed step
-  int32_t* lb_queue;            // [N] growth BFS queue of scenes kept in global memory
+  int32_t* lb_queue;            // [N] growth BFS queue
   uint32_t* lb_visit;           // [N/32+1] growth BFS visited bits of scenes kept in global memory
+  uint32_t* lb_bridge;          // [N/32+1] bridge bits (Alg. 7) of scenes kept in global memory
   // scalars
   int32_t* scal;                // [SC_COUNT]
 };

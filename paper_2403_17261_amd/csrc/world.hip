@@ -179,6 +179,7 @@ struct ovl_world {
     wp.lb_mask = alloc<uint64_t>(lb_allocs, Np, ok);
     wp.lb_queue = alloc<int32_t>(lb_allocs, Np, ok);
     wp.lb_visit = alloc<uint32_t>(lb_allocs, Np / 32 + 1, ok);
+    wp.lb_bridge = alloc<uint32_t>(lb_allocs, Np / 32 + 1, ok);
     if (ok) ok = hipMemsetAsync(wp.lb_visit, 0, (Np / 32 + 1) * sizeof(uint32_t), stream) == hipSuccess &&
                  hipStreamSynchronize(stream) == hipSuccess;
     if (!ok) free_group(lb_allocs);
@@ -805,6 +806,7 @@ ovl_status ovl_step(ovl_world* w, int32_t n_steps, ovl_step_stats* stats, int32_
   stats->n_copies = sc[SC_NCOPY];
   stats->n_replicas = sc[SC_NREP];
   stats->n_overlap = sc[SC_NOVERLAP];
+  stats->n_lb_changes = sc[SC_LB_CHANGES];
   stats->steps = n_steps;
   stats->iters_total = it1[0] - it0[0];
   stats->n_unconverged = (int32_t)(it1[1] - it0[1]);
