@@ -296,7 +296,7 @@ def bench_bowl_lb(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_lb(sc, tol, cap, n_steps=100):
+def cpu_baseline_lb(sc, tol, cap, n_steps=130):
     """The oracle on the first n_steps steps of the same run (carried sets and keys)."""
     import oracle
 
@@ -311,7 +311,7 @@ def cpu_baseline_lb(sc, tol, cap, n_steps=100):
     dt = time.perf_counter() - t0
     return {"value": sc.n_bodies * n_steps / dt, "unit": "body-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle (double precision, one thread, adaptive sweeps to {tol:g}, cap {cap}) on the first "
-                      f"{n_steps} steps of the same run (contacts begin near step 20); mean "
+                      f"{n_steps} steps of the same run (contacts begin near step 20, the pile forms after 100); mean "
                       f"{sweeps / n_steps:.0f} sweeps per step, {dt:.1f} s"}
 
 
