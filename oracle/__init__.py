@@ -64,7 +64,7 @@ class _Params(C.Structure):
                 ("adaptive", C.c_int32), ("warmstart", C.c_int32), ("halo_k", C.c_int32), ("beta", C.c_int32),
                 ("brute_force_contacts", C.c_int32), ("seed", C.c_uint32), ("learned", C.c_int32),
                 ("mlp", C.c_void_p), ("forced_guard", C.c_void_p), ("lb_masks", C.c_void_p),
-                ("lb_depth", C.c_int32)]
+                ("lb_depth", C.c_int32), ("equal_weights", C.c_int32)]
 
 
 class _Cache(C.Structure):
@@ -154,7 +154,7 @@ def mlp_infer(params, x12):
 
 DEFAULTS = dict(dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), cfm=0.0, erp=0.2, max_iters=20, tol=1e-4,
                 adaptive=False, warmstart=True, halo_k=1, beta=4, seed=0, brute_force=False, mlp=None,
-                forced_guard=None, lb_masks=None, lb_depth=0)
+                forced_guard=None, lb_masks=None, lb_depth=0, equal_weights=False)
 
 
 def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced_iters=None, **kw):
@@ -197,6 +197,7 @@ def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced
         pr.mlp = _ptr(arr(p["mlp"], np.float32))
     if p["forced_guard"] is not None:
         pr.forced_guard = _ptr(arr(p["forced_guard"], np.int32))
+    pr.equal_weights = int(bool(p["equal_weights"]))
     if p["lb_masks"] is not None:
         pr.lb_masks = _ptr(arr(p["lb_masks"], np.uint64))
         pr.lb_depth = int(p["lb_depth"])
@@ -232,6 +233,7 @@ def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced
             out["rho_exact"], out["rho_sum"], out["joint_violation"] = st_[0], st_[1], st_[2]
             out["n_overlap"], out["max_colours"], out["max_iters"] = int(st_[3]), int(st_[4]), int(st_[5])
             out["error_code"], out["unconverged"] = int(st_[6]), int(st_[7])
+            out["joint_violation_sum"] = st_[8]
         if err:
             raise RuntimeError("oracle: " + err)
         return out

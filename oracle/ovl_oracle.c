@@ -900,8 +900,8 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
   const int64_t N = sc->n_bodies;
   const int S = sc->n_scenes;
   const double h = prm->dt;
-  double* stats = (double*)xalloc(8 * sizeof(double));
-  put(res, ORC_STATS, stats, 8);
+  double* stats = (double*)xalloc(9 * sizeof(double));
+  put(res, ORC_STATS, stats, 9);
 
   /* ---- partitions: global ids, each scene owns a contiguous range ---- */
   int32_t* pbase = (int32_t*)xalloc((size_t)(S + 1) * sizeof(int32_t));
@@ -1068,6 +1068,8 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
       repD[r] = D[b];
       if (nw == 1)
         repW[r] = 1.0;
+      else if (prm->equal_weights)
+        repW[r] = 1.0 / (double)nw;
       else if (dsum > 0.0)
         repW[r] = (D[b] > 0 ? 1.0 / (double)D[b] : 0.0) / dsum;
       else
@@ -1596,8 +1598,8 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
   }
   put(res, ORC_STATE, out, 13 * N);
 
-  /* ---- joint violation of the blended state ---- */
-  double jviol = 0.0;
+  /* ---- joint violation of the blended state (largest and summed norm) ---- */
+  double jviol = 0.0, jviol_sum = 0.0;
   for (int64_t j = 0; j < sc->n_joints; ++j) {
     int32_t a = sc->joint_ab[2 * j], b = sc->joint_ab[2 * j + 1];
     const float* an = sc->joint_anchor + 6 * j;
@@ -1612,6 +1614,7 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
       e2 += d * d;
     }
     if (sqrt(e2) > jviol) jviol = sqrt(e2);
+    jviol_sum += sqrt(e2);
   }
 
   int max_it = 0;
@@ -1625,6 +1628,7 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
   stats[5] = (double)max_it;
   stats[6] = colour_overflow ? 2.0 : 0.0;
   stats[7] = (double)unconverged;
+  stats[8] = jviol_sum;
   if (colour_overflow) snprintf(res->err, sizeof res->err, "more than 64 colours needed");
 
   free(rep);

@@ -53,6 +53,9 @@ typedef struct {
    * step meets the third rule in the next). */
   const uint64_t* lb_masks;
   int32_t lb_depth;             /* growth depth gamma of Alg. 6 (>= 0) */
+  /* 1: every overlap body blends its replicas with equal weights 1/|W|, the
+   * naive choice section 5.3 compares the geodesic weights against */
+  int32_t equal_weights;
 } orc_params;
 
 #define ORC_MLP_IN 12
