@@ -17,6 +17,12 @@ the naive division of the body list, growth depth 0, worker sets updated from
 every step's new contacts; first 600 steps.  Also reports the per-worker body
 and contact distributions over the run and the same run without balancing.
 
+--workload accuracy: the accuracy study on the 51,200-link chains (256
+chains of 200 ball-jointed spheres over 16 static spheres, 16 x-slabs, h
+1/120 s, 40 sweeps, 500 steps): overlap depth k = 1..4 (gamma = k - 1) with
+geodesic and with equal blend weights, and one partition as the reference;
+joint violation and total residual sampled every 25 steps.
+
 --workload batched: 512 independent bowl scenes (log-uniform 200..5000
 spheres, 1..6 k-means partitions each, fixed at the start), 30 sweeps per
 step, all in one world: the autotuned, graph-replayed launch against the
@@ -296,6 +302,70 @@ def bench_bowl_lb(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_accuracy(args):
+    """Section 6's error measures on the chains: geodesic against equal weights, and the overlap depth."""
+    import torch
+
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    sc = scenes.config3(0)
+    steps = args.steps or sc.steps
+    every = 25
+    runs = []
+    variants = [(k, wmode) for k in (1, 2, 3, 4) for wmode in ("geodesic", "equal")] + [(0, "one partition")]
+    for k, wmode in variants:
+        p = ovl.make_params(dt=sc.dt, max_iters=sc.iters, mode=ovl.MODE_FIXED, warmstart=ovl.WARM_PLAIN,
+                            weights=ovl.WEIGHTS_EQUAL if wmode == "equal" else ovl.WEIGHTS_GEODESIC)
+        w = ovl.World(sc, p)
+        if k == 0:
+            w.set_partitions(np.zeros(sc.n_bodies, np.int32), np.array([1], np.int32), halo_k=1, beta=sc.beta)
+        else:
+            w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=k, beta=sc.beta)
+        samples = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(every, steps + 1, every):
+            w.step(every - 1)
+            st = w.step(1, stats=True, exact=True)
+            samples.append((t, st["joint_violation_max"], st["joint_violation_sum"], st["resid_exact_sum"],
+                            st["resid_exact"], st["n_overlap"], st["n_replicas"]))
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        w.close()
+        a = np.array(samples, np.float64)
+        half = a[len(a) // 2:]
+        r = {"k": k, "weights": wmode, "ms_per_step": 1e3 * secs / steps,
+             "joint_violation_sum_mean_second_half": float(half[:, 2].mean()),
+             "joint_violation_max_mean_second_half": float(half[:, 1].mean()),
+             "joint_violation_max_worst": float(a[:, 1].max()),
+             "total_residual_mean_second_half": float(half[:, 3].mean()),
+             "overlap_bodies_mean": float(a[:, 5].mean()), "replicas_mean": float(a[:, 6].mean()),
+             "series": [[int(x[0]), round(float(x[2]), 6), round(float(x[3]), 4)] for x in a]}
+        runs.append(r)
+        log(f"[accuracy k={k} {wmode}] joint violation sum {r['joint_violation_sum_mean_second_half']:.4e} m "
+            f"(max {r['joint_violation_max_mean_second_half']:.3e}), total residual "
+            f"{r['total_residual_mean_second_half']:.4e} m/s, overlap {r['overlap_bodies_mean']:.0f}, "
+            f"{r['ms_per_step']:.2f} ms/step")
+    head = next(r for r in runs if r["k"] == sc.halo_k and r["weights"] == "geodesic")
+    out = {
+        "metric": "summed ball-joint violation |C| of the blended state, mean over steps 250-500 (lower is better)",
+        "value": head["joint_violation_sum_mean_second_half"], "unit": "m", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": head["ms_per_step"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": (f"chains: 256 chains of 200 ball-jointed spheres r 0.1 m, m 0.5 kg, over 16 static "
+                         f"spheres, 16 x-slab partitions, h 1/120 s, 40 sweeps (fixed), beta 4, {steps} steps; "
+                         f"exact diagnostics every {every} steps"),
+            "reported": f"k = {sc.halo_k}, geodesic weights",
+            "runs": runs,
+        },
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_lb(sc, tol, cap, n_steps=130):
     """The oracle on the first n_steps steps of the same run (carried sets and keys)."""
     import oracle
@@ -357,7 +427,7 @@ def per_scene_loop(sc, p, args, timed):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["tower", "bowl", "bowl-lb", "batched"], default="tower")
+    ap.add_argument("--workload", choices=["tower", "bowl", "bowl-lb", "batched", "accuracy"], default="tower")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps first (default 10; batched: 150, so the piles have formed)")
@@ -396,6 +466,9 @@ def main():
         return
     if args.workload == "bowl-lb":
         bench_bowl_lb(args)
+        return
+    if args.workload == "accuracy":
+        bench_accuracy(args)
         return
     if args.workload == "batched":
         if args.warmup is None:

@@ -76,6 +76,9 @@ typedef struct {
 
 enum { OVL_MODE_FIXED = 0, OVL_MODE_ADAPTIVE = 1 };
 enum { OVL_WARM_NONE = 0, OVL_WARM_PLAIN = 1, OVL_WARM_LEARNED = 2 };
+/* Blend weights of the overlap bodies: geodesic (section 5.3, Eq. 15-16,
+ * Alg. 5) or equal 1/|W| (the naive weights section 5.3 compares against). */
+enum { OVL_WEIGHTS_GEODESIC = 0, OVL_WEIGHTS_EQUAL = 1 };
 
 /* Parameters of the warm-start network 12 -> 64 -> 64 -> 3 (ReLU), flat:
  * W1[12][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3], input index first. */
@@ -96,6 +99,7 @@ typedef struct {
   int32_t mode;       /* OVL_MODE_* */
   int32_t warmstart;  /* OVL_WARM_* */
   uint32_t seed;      /* colouring priority seed */
+  int32_t weights;    /* OVL_WEIGHTS_* */
 } ovl_params;
 
 /* Device context: the stream every kernel runs on (NULL = the null stream)
@@ -122,6 +126,12 @@ typedef struct {
   float resid_sweep;       /* largest last-sweep residual max |A_rr dlambda| over partitions (m/s) */
   float resid_exact;       /* natural-map residual of the final iterate (computed when requested) */
   int64_t n_lb_changes;    /* contacts whose load-balancing rule changed a worker set (last step) */
+  /* computed with resid_exact (last step): the natural-map residual summed over
+   * every row of every partition (the paper's total residual, section 6), and
+   * the largest and the summed norm |C| of the ball joints at the blended state */
+  double resid_exact_sum;
+  double joint_violation_max;
+  double joint_violation_sum;
 } ovl_step_stats;
 
 /* Create a world from a scene description.  Every body starts in partition 0

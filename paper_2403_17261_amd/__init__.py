@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ovl.h")
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_NONFINITE, ERR_DEVICE, NOT_CONVERGED = range(7)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "NONFINITE", 5: "DEVICE", 6: "NOT_CONVERGED"}
 MODE_FIXED, MODE_ADAPTIVE = 0, 1
+WEIGHTS_GEODESIC, WEIGHTS_EQUAL = 0, 1
 WARM_NONE, WARM_PLAIN, WARM_LEARNED = 0, 1, 2
 MLP_PARAMS = 5187
 
@@ -54,7 +55,7 @@ class ovl_world_desc(C.Structure):
 class ovl_params(C.Structure):
     _fields_ = [("dt", C.c_float), ("gravity", C.c_float * 3), ("cfm", C.c_float), ("erp", C.c_float),
                 ("tol", C.c_float), ("max_iters", C.c_int32), ("mode", C.c_int32), ("warmstart", C.c_int32),
-                ("seed", C.c_uint32)]
+                ("seed", C.c_uint32), ("weights", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -69,7 +70,9 @@ class ovl_step_stats(C.Structure):
     _fields_ = [("n_contacts", C.c_int64), ("n_copies", C.c_int64), ("n_replicas", C.c_int64),
                 ("n_overlap", C.c_int64), ("max_colours", C.c_int32), ("max_iters", C.c_int32),
                 ("n_unconverged", C.c_int32), ("steps", C.c_int32), ("iters_total", C.c_int64),
-                ("resid_sweep", C.c_float), ("resid_exact", C.c_float), ("n_lb_changes", C.c_int64)]
+                ("resid_sweep", C.c_float), ("resid_exact", C.c_float), ("n_lb_changes", C.c_int64),
+                ("resid_exact_sum", C.c_double), ("joint_violation_max", C.c_double),
+                ("joint_violation_sum", C.c_double)]
 
 
 class ovl_counters(C.Structure):
@@ -169,12 +172,13 @@ def _p(a):
 
 
 def make_params(dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), cfm=0.0, erp=0.2, tol=1e-4, max_iters=20,
-                mode=MODE_FIXED, warmstart=WARM_PLAIN, seed=0) -> ovl_params:
+                mode=MODE_FIXED, warmstart=WARM_PLAIN, seed=0, weights=WEIGHTS_GEODESIC) -> ovl_params:
     p = ovl_params()
     p.dt = dt
     p.gravity[0], p.gravity[1], p.gravity[2] = gravity
     p.cfm, p.erp, p.tol = cfm, erp, tol
     p.max_iters, p.mode, p.warmstart, p.seed = int(max_iters), int(mode), int(warmstart), int(seed) & 0xFFFFFFFF
+    p.weights = int(weights)
     return p
 
 

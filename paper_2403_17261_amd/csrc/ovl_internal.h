@@ -60,6 +60,7 @@ struct WP {
   // parameters
   float dt, gx, gy, gz, cfm, erp, tol;
   int32_t max_iters, adaptive, warmstart, halo_k, beta;
+  int32_t equal_w;               // 1: equal blend weights instead of geodesic ones
   uint32_t seed;
   int32_t forced;                // 1: part_force_iters holds each partition's sweep count
   // static body data
@@ -184,6 +185,8 @@ struct WP {
   int32_t* part_iters;          // [G]
   int32_t* part_nstatic;        // [G] contact copies with a static body
   float* part_resid;            // [G]
+  float* part_rsum;             // [G] natural-map residual summed over the partition's rows
+  float* joint_viol;            // [J] |C| of every ball joint at the blended state
   float* stat_f;                // [4]: exact residual
   int64_t* stat_i64;            // [8]: 0 sum over steps of the largest sweep count, 1 unconverged partitions,
                                 //      2 algorithmic bytes of the sweeps, 3 sweeps summed over partitions,

@@ -1113,7 +1113,7 @@ __global__ void k_blend(WP w) {
   float q0[4];
   for (int k = 0; k < n; ++k) {
     const int D = w.rep_D_bm[bm0 + k];
-    const float wt = sum > 0.0f ? (D > 0 ? 1.0f / (float)D : 0.0f) / sum : 1.0f / (float)n;
+    const float wt = (sum > 0.0f && !w.equal_w) ? (D > 0 ? 1.0f / (float)D : 0.0f) / sum : 1.0f / (float)n;
     w.rep_w_bm[bm0 + k] = wt;
     const int r = w.rep_pm_of_bm[bm0 + k];
     float s[13];
@@ -1233,7 +1233,7 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
   const int r0 = w.part_rep_off[p];
   const int s0 = w.part_copy_off[p], s1 = w.part_copy_off[p + 1];
   const int64_t RC = w.Rcap;
-  float e = 0.0f;
+  float e = 0.0f, esum = 0.0f;
   for (int slot = s0 + threadIdx.x; slot < s1; slot += 256) {
     Rec R;
     if (w.has_caps)
@@ -1296,10 +1296,42 @@ __global__ __launch_bounds__(256) void k_exact_resid(WP w) {
       const float wv = vr[k] + bias[k] + w.cfm * l[k];
       const float pr = fminf(fmaxf(l[k] - wv * invd[k], lo[k]), hi[k]);
       e = fmaxf(e, fabsf(l[k] - pr) / invd[k]);
+      esum += fabsf(l[k] - pr) / invd[k];
     }
   }
   e = block_max<256>(e, red);
   if (threadIdx.x == 0) atomicMax((int*)&w.stat_f[0], __float_as_int(e));
+  // summed residual in a fixed order: waves, then the block
+  esum = wave_sum_f(esum);
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x >> 6] = esum;
+  __syncthreads();
+  if (threadIdx.x == 0) w.part_rsum[p] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// |C| of every ball joint at the blended state (section 6 reports joint violation)
+__global__ void k_joint_viol(WP w) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= w.J || step_failed(w)) return;
+  const int N = w.N;
+  const int a = w.j_ab[2 * j], b = w.j_ab[2 * j + 1];
+  const float* an = w.j_anchor + 6 * j;
+  float d[3];
+  const int bod[2] = {a, b};
+  float p[2][3];
+  for (int s = 0; s < 2; ++s) {
+    const int v = bod[s];
+    const float qw = w.st[3 * N + v], qx = w.st[4 * N + v], qy = w.st[5 * N + v], qz = w.st[6 * N + v];
+    const float ax = an[3 * s], ay = an[3 * s + 1], az = an[3 * s + 2];
+    // R(q) a = a + 2 qw (u x a) + 2 u x (u x a), u = (qx, qy, qz)
+    const float cx = qy * az - qz * ay, cy = qz * ax - qx * az, cz = qx * ay - qy * ax;
+    const float ex = qy * cz - qz * cy, ey = qz * cx - qx * cz, ez = qx * cy - qy * cx;
+    p[s][0] = w.st[0 * N + v] + ax + 2.0f * (qw * cx + ex);
+    p[s][1] = w.st[1 * N + v] + ay + 2.0f * (qw * cy + ey);
+    p[s][2] = w.st[2 * N + v] + az + 2.0f * (qw * cz + ez);
+  }
+  for (int k = 0; k < 3; ++k) d[k] = p[0][k] - p[1][k];
+  w.joint_viol[j] = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
 }
 
 }  // namespace
@@ -1414,6 +1446,10 @@ hipError_t launch_solve_post(const WP& w, hipStream_t s, bool exact_residual) {
   }
   if (w.N > 0) {
     k_blend<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+  }
+  if (exact_residual && w.J > 0) {
+    k_joint_viol<<<nblocks(w.J, kBlock), kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
   if (w.Mcap > 0) {

@@ -214,6 +214,7 @@ struct ovl_world {
     w.part_rho0 = alloc<float>(g, 2 * (size_t)G_ + 2, ok);
     w.part_force_guard = alloc<int32_t>(g, G_ + 1, ok);
     w.part_resid = alloc<float>(g, G_ + 1, ok);
+    w.part_rsum = alloc<float>(g, G_ + 1, ok);
     w.part_order = alloc<int32_t>(g, G_ + 1, ok);
     return ok;
   }
@@ -231,6 +232,7 @@ struct ovl_world {
     wp.adaptive = p.mode == OVL_MODE_ADAPTIVE;
     wp.warmstart = p.warmstart == OVL_WARM_PLAIN;
     wp.seed = p.seed;
+    wp.equal_w = p.weights == OVL_WEIGHTS_EQUAL ? 1 : 0;
   }
 
   bool read_scal(int32_t* out) {
@@ -361,6 +363,7 @@ ovl_status validate_params(const ovl_params* p, std::string& err) {
   else if (p->mode != OVL_MODE_FIXED && p->mode != OVL_MODE_ADAPTIVE) err = "bad mode";
   else if (p->warmstart != OVL_WARM_NONE && p->warmstart != OVL_WARM_PLAIN) err = "bad warmstart mode";
   else if (!(p->tol >= 0.0f)) err = "tol must be >= 0";
+  else if (p->weights != OVL_WEIGHTS_GEODESIC && p->weights != OVL_WEIGHTS_EQUAL) err = "bad weights mode";
   else if (!std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2]))
     err = "gravity must be finite";
   else
@@ -548,6 +551,7 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   float* j_anchor = w->alloc<float>(g, 6 * (size_t)std::max(J, 1), ok);
   int32_t* jadj_off_d = w->alloc<int32_t>(g, N + 1, ok);
   int32_t* jadj_d = w->alloc<int32_t>(g, std::max<size_t>(jadj.size(), 1), ok);
+  wp.joint_viol = w->alloc<float>(g, std::max(J, 1), ok);
   wp.owner_local = w->alloc<int32_t>(g, Np, ok);
   wp.st = w->alloc<float>(g, (size_t)13 * Np, ok);
   wp.cell = w->alloc<int32_t>(g, (size_t)3 * Np, ok);
@@ -816,6 +820,21 @@ ovl_status ovl_step(ovl_world* w, int32_t n_steps, ovl_step_stats* stats, int32_
     stats->resid_sweep = std::max(stats->resid_sweep, resid[g]);
   }
   stats->resid_exact = compute_exact_residual ? sf[0] : -1.0f;
+  stats->resid_exact_sum = -1.0;
+  stats->joint_violation_max = stats->joint_violation_sum = -1.0;
+  if (compute_exact_residual) {
+    std::vector<float> rs(w->G), jv(w->J);
+    if (hipMemcpy(rs.data(), w->wp.part_rsum, w->G * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+        (w->J > 0 && hipMemcpy(jv.data(), w->wp.joint_viol, w->J * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess))
+      return w->fail(OVL_ERR_DEVICE, "copy failed");
+    stats->resid_exact_sum = 0.0;
+    for (float x : rs) stats->resid_exact_sum += x;
+    stats->joint_violation_max = stats->joint_violation_sum = 0.0;
+    for (float x : jv) {
+      stats->joint_violation_max = std::max(stats->joint_violation_max, (double)x);
+      stats->joint_violation_sum += x;
+    }
+  }
   if (stats->n_unconverged > 0) return w->fail(OVL_NOT_CONVERGED, "some partitions hit the sweep cap");
   return OVL_OK;
 }

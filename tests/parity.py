@@ -32,7 +32,8 @@ def adjacency_sets(off, adj):
 def oracle_kwargs(sc, params, halo_k, beta):
     return dict(dt=params.dt, gravity=tuple(params.gravity), cfm=params.cfm, erp=params.erp,
                 max_iters=params.max_iters, tol=params.tol, adaptive=params.mode == 1,
-                warmstart=params.warmstart == 1, seed=params.seed, halo_k=halo_k, beta=beta)
+                warmstart=params.warmstart == 1, seed=params.seed, halo_k=halo_k, beta=beta,
+                equal_weights=params.weights == 1)
 
 
 def check_state(sc, gpu, ref, dt, label=""):
