@@ -627,61 +627,49 @@ __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcp
 //   J_t1 v = t1.(v_b - v_a) - t2.(l_a w_a + l_b w_b)
 //   J_t2 v = t2.(v_b - v_a) + t1.(l_a w_a + l_b w_b)
 // and the impulse dl of a row moves v_a by -dl/m_a d, v_b by +dl/m_b d, and the
-// spins by the matching lever-arm terms.  `solve` false applies lam as given
-// (warm start) instead of projecting.
+// spins by the matching lever-arm terms.  For such a contact the three rows
+// are decoupled (J_i M^-1 J_j^T = 0 for i != j): an impulse on one row leaves
+// the other rows' velocities unchanged.  Solving the rows in order n, t1, t2
+// therefore only needs the velocities before the contact, and the three
+// impulses are applied together.  `solve` false applies lam as given (warm
+// start) instead of projecting.
 template <bool solve>
 __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl) {
   const f3 n = mk(R.r0.x, R.r0.y, R.r0.z);
   f3 t1, t2;
   tangents_from(n, R.r0.w, t1, t2);
   const float la = R.r1.x, lb = R.r1.y, bias = R.r1.z, mu = R.r1.w;
-  float dl;
-  // normal
-  if (solve) {
-    const f3 dv = sub(B.v, A.v);
-    const float wv = dot(n, dv) + bias + cfm * lam.x;
-    const float nl = fmaxf(lam.x - wv * R.r2.x, 0.0f);
-    dl = nl - lam.x;
-    lam.x = nl;
-    rl = fmaxf(rl, fabsf(dl) * R.r2.z);
-  } else {
-    dl = lam.x;
-  }
-  A.v = sub(A.v, scale(n, A.im * dl));
-  B.v = add(B.v, scale(n, B.im * dl));
-  const float hi = mu * lam.x;
-  // tangent 1
+  float d0, d1, d2;
   if (solve) {
     const f3 dv = sub(B.v, A.v);
     const f3 sw = add(scale(A.w, la), scale(B.w, lb));
-    const float wv = dot(t1, dv) - dot(t2, sw) + cfm * lam.y;
-    const float nl = fminf(fmaxf(lam.y - wv * R.r2.y, -hi), hi);
-    dl = nl - lam.y;
-    lam.y = nl;
-    rl = fmaxf(rl, fabsf(dl) * R.r2.w);
+    // normal
+    const float un = dot(n, dv) + bias + cfm * lam.x;
+    const float ln = fmaxf(lam.x - un * R.r2.x, 0.0f);
+    d0 = ln - lam.x;
+    lam.x = ln;
+    // friction box of the new normal impulse
+    const float hi = mu * ln;
+    const float u1 = dot(t1, dv) - dot(t2, sw) + cfm * lam.y;
+    const float l1 = fminf(fmaxf(lam.y - u1 * R.r2.y, -hi), hi);
+    d1 = l1 - lam.y;
+    lam.y = l1;
+    const float u2 = dot(t2, dv) + dot(t1, sw) + cfm * lam.z;
+    const float l2 = fminf(fmaxf(lam.z - u2 * R.r2.y, -hi), hi);
+    d2 = l2 - lam.z;
+    lam.z = l2;
+    rl = fmaxf(rl, fmaxf(fabsf(d0) * R.r2.z, fmaxf(fabsf(d1), fabsf(d2)) * R.r2.w));
   } else {
-    dl = lam.y;
+    d0 = lam.x;
+    d1 = lam.y;
+    d2 = lam.z;
   }
-  A.v = sub(A.v, scale(t1, A.im * dl));
-  B.v = add(B.v, scale(t1, B.im * dl));
-  A.w = sub(A.w, scale(t2, A.ii * la * dl));
-  B.w = sub(B.w, scale(t2, B.ii * lb * dl));
-  // tangent 2
-  if (solve) {
-    const f3 dv = sub(B.v, A.v);
-    const f3 sw = add(scale(A.w, la), scale(B.w, lb));
-    const float wv = dot(t2, dv) + dot(t1, sw) + cfm * lam.z;
-    const float nl = fminf(fmaxf(lam.z - wv * R.r2.y, -hi), hi);
-    dl = nl - lam.z;
-    lam.z = nl;
-    rl = fmaxf(rl, fabsf(dl) * R.r2.w);
-  } else {
-    dl = lam.z;
-  }
-  A.v = sub(A.v, scale(t2, A.im * dl));
-  B.v = add(B.v, scale(t2, B.im * dl));
-  A.w = add(A.w, scale(t1, A.ii * la * dl));
-  B.w = add(B.w, scale(t1, B.ii * lb * dl));
+  const f3 P = add(add(scale(n, d0), scale(t1, d1)), scale(t2, d2));
+  const f3 Q = sub(scale(t2, d1), scale(t1, d2));
+  A.v = sub(A.v, scale(P, A.im));
+  B.v = add(B.v, scale(P, B.im));
+  A.w = sub(A.w, scale(Q, A.ii * la));
+  B.w = sub(B.w, scale(Q, B.ii * lb));
 }
 
 // Ball joint, rows along -e_k: J_k v = (v_a + w_a x r_a - v_b - w_b x r_b)_k;
