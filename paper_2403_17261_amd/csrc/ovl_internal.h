@@ -142,6 +142,7 @@ struct WP {
   int32_t* cp_ib;               // [Mcap]
   int32_t* cp_colour;           // [Mcap]
   int32_t* cp_slot;             // [Mcap]
+  int32_t* cp_inv;              // [Mcap] slot -> copy (scratch of the slot order)
   int32_t* inc_off;             // [2*Rcap] replica -> first incident copy, then incident-copy counts
   int32_t* inc;                 // [2*Mcap]
   int32_t* part_col_off;        // [G*65]

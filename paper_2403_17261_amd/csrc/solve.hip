@@ -1387,12 +1387,101 @@ hipError_t pgs_occupancy(int cfg, bool caps, int* per_cu_lds, int* per_cu_glob) 
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------- slot order in a colour ----
+// The copies of one colour share no replica, so any order of their slots gives
+// the same sweep.  The order is chosen for the solver's LDS gathers: thread t
+// of a colour reads replicas ia and ib of slot t, and 16 consecutive threads
+// read without bank conflicts when their ia (and their ib) differ modulo 16
+// (a replica's 16 B velocity entry sits in bank group ia mod 16).  Copies are
+// grouped by d = (ia - ib) mod 16 (16 for a static second body), and inside a
+// group dealt out round-robin over ia mod 16: each round then holds distinct
+// ia residues, and, d being fixed, distinct ib residues.  Ranks are taken in
+// the previous (uid) order, so the result is deterministic.
+constexpr int kSpreadBS = 1024;
+constexpr int kSpreadWaves = kSpreadBS / 64;
+constexpr int kSpreadKeys = 17 * 16;
+
+__global__ __launch_bounds__(kSpreadBS) void k_slot_spread(WP w) {
+  __shared__ int tab[kSpreadWaves][kSpreadKeys];
+  __shared__ int run[kSpreadWaves][kSpreadKeys];
+  __shared__ int base[kSpreadWaves][18];
+  __shared__ int coff[kColStride];
+  __shared__ int skip_s;
+  const int p = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  if (tid == 0) skip_s = (w.scal[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP)) ? 1 : 0;
+  __syncthreads();
+  if (skip_s) return;
+  const int u0 = w.part_copy_off[p], u1 = w.part_copy_off[p + 1];
+  const int ncol = w.part_ncol[p];
+  if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
+  for (int u = u0 + tid; u < u1; u += kSpreadBS) w.cp_inv[w.cp_slot[u]] = u;
+  __syncthreads();
+  int* T = tab[wave];
+  int* Rn = run[wave];
+  int* Bs = base[wave];
+  auto key_of = [&](int u) {
+    const int ia = w.cp_ia[u], ib = w.cp_ib[u];
+    const int d = ib < 0 ? 16 : ((ia - ib) & 15);
+    return d * 16 + (ia & 15);
+  };
+  for (int c = wave; c < ncol; c += kSpreadWaves) {
+    const int cb = u0 + coff[c], n = coff[c + 1] - coff[c];
+    for (int k = lane; k < kSpreadKeys; k += 64) {
+      T[k] = 0;
+      Rn[k] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < n; i += 64) atomicAdd(&T[key_of(w.cp_inv[cb + i])], 1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    // group sizes and starts: lane d < 17 sums its group
+    int nd = 0;
+    if (lane < 17)
+      for (int r = 0; r < 16; ++r) nd += T[lane * 16 + r];
+    const int inc = wave_incl_scan(nd);
+    if (lane < 17) Bs[lane] = inc - nd;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int i0 = 0; i0 < n; i0 += 64) {
+      const int i = i0 + lane;
+      const bool valid = i < n;
+      const int u = valid ? w.cp_inv[cb + i] : -1;
+      const int key = valid ? key_of(u) : 511;
+      // lanes holding the same key (nine ballots over its bits)
+      uint64_t peers = ~0ull;
+#pragma unroll
+      for (int b = 0; b < 9; ++b) {
+        const uint64_t bal = __ballot((key >> b) & 1);
+        peers &= ((key >> b) & 1) ? bal : ~bal;
+      }
+      const int rank = __popcll(peers & lanemask_lt());
+      const int j = valid ? Rn[key] + rank : 0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      if (valid && rank == 0) Rn[key] += __popcll(peers);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        const int d = key >> 4, r = key & 15;
+        int pos = Bs[d];
+        for (int q = 0; q < 16; ++q) {
+          const int cq = T[d * 16 + q];
+          pos += min(cq, j) + ((q < r && cq > j) ? 1 : 0);
+        }
+        w.cp_slot[u] = cb + pos;
+      }
+    }
+  }
+}
+
 hipError_t launch_solve_pre(const WP& w, hipStream_t s) {
   hipError_t e;
   if (w.G > 0) {
     k_part_order<<<nblocks(w.G, kOrderBS), kOrderBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
     k_colour<<<w.G, kColBS, 0, s>>>(w);
+    k_slot_spread<<<w.G, kSpreadBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
   if (w.Mcap > 0) {

@@ -155,6 +155,7 @@ struct ovl_world {
     w.cp_ib = alloc<int32_t>(g, Mcap, ok);
     w.cp_colour = alloc<int32_t>(g, Mcap, ok);
     w.cp_slot = alloc<int32_t>(g, Mcap, ok);
+    w.cp_inv = alloc<int32_t>(g, Mcap, ok);
     w.r_rec = alloc<float4>(g, (size_t)3 * Mcap, ok);
     w.r_gen = alloc<float4>(g, w.has_caps ? (size_t)2 * Mcap : 1, ok);
     w.rep_ax = alloc<float4>(g, w.has_caps ? (size_t)Rcap : 1, ok);
