@@ -690,7 +690,22 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
 
 // Ball joint, rows along -e_k: J_k v = (v_a + w_a x r_a - v_b - w_b x r_b)_k;
 // the impulse dl of row k moves v_a by +dl/m_a e_k and w_a by +dl I_a^-1 (r_a x e_k),
-// and body b the opposite way.
+// and body b the opposite way.  The rows are written out per axis so that no
+// product with a zero component of e_k is formed.
+__device__ __forceinline__ f3 cross_axis(f3 r, int k) {
+  // r x e_k
+  return k == 0 ? mk(0.0f, r.z, -r.y) : (k == 1 ? mk(-r.z, 0.0f, r.x) : mk(r.y, -r.x, 0.0f));
+}
+
+__device__ __forceinline__ void add_axis(f3& v, int k, float s) {
+  if (k == 0)
+    v.x += s;
+  else if (k == 1)
+    v.y += s;
+  else
+    v.z += s;
+}
+
 template <bool solve, bool kGen = false>
 __device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl,
                                            float4 axA = float4{}, float4 axB = float4{}) {
@@ -702,9 +717,10 @@ __device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float c
   for (int k = 0; k < 3; ++k) {
     float dl;
     if (solve) {
-      const f3 pa = add(A.v, cross(A.w, ra));
-      const f3 pb = add(B.v, cross(B.w, rb));
-      const float vr = k == 0 ? pa.x - pb.x : (k == 1 ? pa.y - pb.y : pa.z - pb.z);
+      // (v_a + w_a x r_a - v_b - w_b x r_b)_k
+      const f3 ca = cross(A.w, ra), cb = cross(B.w, rb);
+      const float vr = k == 0 ? (A.v.x + ca.x) - (B.v.x + cb.x)
+                              : (k == 1 ? (A.v.y + ca.y) - (B.v.y + cb.y) : (A.v.z + ca.z) - (B.v.z + cb.z));
       const float wv = vr + bias[k] + cfm * l[k];
       const float nl = l[k] - wv * invd[k];
       dl = nl - l[k];
@@ -713,15 +729,31 @@ __device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float c
     } else {
       dl = l[k];
     }
-    const f3 e = mk(k == 0 ? 1.0f : 0.0f, k == 1 ? 1.0f : 0.0f, k == 2 ? 1.0f : 0.0f);
-    A.v = add(A.v, scale(e, A.im * dl));
-    B.v = sub(B.v, scale(e, B.im * dl));
+    add_axis(A.v, k, A.im * dl);
+    add_axis(B.v, k, -B.im * dl);
+    const f3 xa = cross_axis(ra, k), xb = cross_axis(rb, k);
     if (kGen) {
-      A.w = add(A.w, scale(inv_inertia(A.ii, mk(axA.x, axA.y, axA.z), axA.w, cross(ra, e)), dl));
-      B.w = sub(B.w, scale(inv_inertia(B.ii, mk(axB.x, axB.y, axB.z), axB.w, cross(rb, e)), dl));
+      A.w = add(A.w, scale(inv_inertia(A.ii, mk(axA.x, axA.y, axA.z), axA.w, xa), dl));
+      B.w = sub(B.w, scale(inv_inertia(B.ii, mk(axB.x, axB.y, axB.z), axB.w, xb), dl));
     } else {
-      A.w = add(A.w, scale(cross(ra, e), A.ii * dl));
-      B.w = sub(B.w, scale(cross(rb, e), B.ii * dl));
+      const float sa = A.ii * dl, sb = B.ii * dl;
+      // only the two nonzero components of r x e_k
+      if (k == 0) {
+        A.w.y += sa * xa.y;
+        A.w.z += sa * xa.z;
+        B.w.y -= sb * xb.y;
+        B.w.z -= sb * xb.z;
+      } else if (k == 1) {
+        A.w.x += sa * xa.x;
+        A.w.z += sa * xa.z;
+        B.w.x -= sb * xb.x;
+        B.w.z -= sb * xb.z;
+      } else {
+        A.w.x += sa * xa.x;
+        A.w.y += sa * xa.y;
+        B.w.x -= sb * xb.x;
+        B.w.y -= sb * xb.y;
+      }
     }
   }
 }
