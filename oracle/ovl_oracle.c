@@ -1239,13 +1239,9 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
 
   /* ---- colouring: within a partition two copies conflict when they share
    * a non-static body.  Greedy colouring in descending priority
-   * (fmix32(uid ^ seed), uid).  A partition of n copies has a palette of
-   * K = min(48, ceil(n / 896)) colours; each copy tries them in cyclic order
-   * from its own start fmix32(uid ^ seed ^ 0x5bd1e995) mod K and takes the
-   * first not used by a conflicting copy already coloured; when all K are
-   * used it takes the smallest free colour above them.  With K = 1 this is
-   * the plain smallest-free-colour greedy.  This fixes the Gauss-Seidel order
-   * (colour, then uid) without changing the method. ---- */
+   * (fmix32(uid ^ seed), uid): each copy takes the smallest colour not used
+   * by a conflicting copy already coloured.  This fixes the Gauss-Seidel
+   * order (colour, then uid) without changing the method. ---- */
   int max_colours = 0;
   int colour_overflow = 0;
   for (int32_t p = 0; p < G; ++p) {
@@ -1275,8 +1271,6 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
       pr[m - m0].idx = m;
     }
     qsort(pr, (size_t)nm, sizeof(prio_t), cmp_prio_desc);
-    int K = (int)((nm + 895) / 896);
-    if (K > 48) K = 48;
     for (int64_t t = 0; t < nm; ++t) {
       copy_t* c = &cp[pr[t].idx];
       uint64_t used = 0;
@@ -1288,15 +1282,7 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
           if (cp[o].colour >= 0) used |= 1ull << cp[o].colour;
         }
       }
-      int ring = -1;
-      if (K > 1) {
-        int st = (int)(orc_fmix32((uint32_t)c->uid ^ prm->seed ^ 0x5bd1e995u) % (uint32_t)K);
-        for (int i = 0; i < K && ring < 0; ++i)
-          if (!(used >> ((st + i) % K) & 1)) ring = (st + i) % K;
-      }
-      if (ring >= 0) {
-        c->colour = ring;
-      } else if (used == ~0ull) {
+      if (used == ~0ull) {
         colour_overflow = 1;
         c->colour = 63;
       } else {

@@ -184,24 +184,8 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   // neighbours.  Every neighbour list is read twice in all, not once per round.
   // Otherwise (larger partitions) the same rounds run on global colours, each
   // round rechecking the uncoloured copies.
-  // Colour choice: a palette of K = min(48, ceil(n / 896)) colours tried
-  // cyclically from the copy's own start, then the smallest free colour above
-  // it.  The classes of a large partition then come out of about equal size
-  // (at most ~900 copies: one pass of a 1024-thread solver workgroup) instead
-  // of the plain greedy's decreasing sizes.  With K = 1 this is the plain
-  // smallest-free-colour rule.  A copy's choice depends only on its
-  // higher-priority neighbours, so the rounds still equal the sequential greedy.
   bool overflow = false;
-  const int K = min(48, (u1 - u0 + 895) / 896);
-  auto pick = [&](uint64_t used, int u) -> int {
-    if (K > 1) {
-      const uint64_t ring = ~used & ((1ull << K) - 1ull);
-      if (ring) {
-        const int st = (int)(fmix32((uint32_t)u ^ w.seed ^ 0x5bd1e995u) % (uint32_t)K);
-        const uint64_t hi = (ring >> st) << st;
-        return __builtin_ctzll(hi ? hi : ring);
-      }
-    }
+  auto pick = [&](uint64_t used) -> int {
     if (used == ~0ull) {
       overflow = true;
       return kMaxColours - 1;
@@ -252,7 +236,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
             if (co >= 0) used |= 1ull << co;
           }
         }
-        col_lds[u - u0] = (signed char)pick(used, u);
+        col_lds[u - u0] = (signed char)pick(used);
         now |= 1u << j;
       }
       todo &= ~now;
@@ -299,7 +283,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
           }
         }
         if (ready)
-          __hip_atomic_store(&w.cp_colour[u], pick(used, u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_store(&w.cp_colour[u], pick(used), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
           pending = true;
       }

@@ -452,10 +452,8 @@ def test_blend_algorithm4(orc):
 # colouring, contacts, tangents, hashing
 # ------------------------------------------------------------------------------------------
 
-def _jones_plassmann(ia, ib, prio, start=None, K=1):
-    """Round-based Jones-Plassmann colouring (independent of the oracle's greedy):
-    a copy takes the first colour free of its higher-priority neighbours, trying
-    its palette 0..K-1 cyclically from start[c], then the smallest above it."""
+def _jones_plassmann(ia, ib, prio):
+    """Round-based Jones-Plassmann colouring (independent of the oracle's greedy)."""
     m = len(ia)
     inc = {}
     for c in range(m):
@@ -473,11 +471,6 @@ def _jones_plassmann(ia, ib, prio, start=None, K=1):
         ready = [c for c in range(m) if col[c] < 0 and all(col[o] >= 0 for o in nb[c] if prio[o] > prio[c])]
         for c in ready:
             used = {col[o] for o in nb[c] if col[o] >= 0 and prio[o] > prio[c]}
-            ring = [(start[c] + i) % K for i in range(K)] if K > 1 else []
-            free = [k for k in ring if k not in used]
-            if free:
-                col[c] = free[0]
-                continue
             k = 0
             while k in used:
                 k += 1
@@ -500,32 +493,6 @@ def test_colouring_is_valid_and_equals_jones_plassmann(orc, seed):
                     assert not ({ia[c], ib[c]} - {-1}) & ({ia[d], ib[d]} - {-1})
         prio = [(orc.fmix32((s + c) ^ seed), s + c) for c in range(e - s)]
         assert list(cols) == _jones_plassmann(list(ia), list(ib), prio)
-
-
-@pytest.mark.parametrize("seed", [0, 777])
-def test_palette_colouring_equals_jones_plassmann(orc, seed):
-    """Partitions of more than 896 copies use a cyclic palette of K colours:
-    still a valid colouring, equal to the parallel rounds, and with K = 1 the
-    plain greedy (the small-lattice test above)."""
-    sc = scenes.config5(0, nx=8, ny=8, nz=16, cols=1)
-    o = orc.step(sc, seed=seed, max_iters=1)
-    s, e = int(o["part_copy_off"][0]), int(o["part_copy_off"][1])
-    m = e - s
-    K = min(48, (m + 895) // 896)
-    assert K >= 3 and K != (m + 1023) // 1024
-    ia, ib = list(o["copy_ia"][s:e]), list(o["copy_ib"][s:e])
-    cols = o["copy_colour"][s:e]
-    owner = {}
-    for c in range(m):
-        for v in (ia[c], ib[c]):
-            if v >= 0:
-                assert (v, cols[c]) not in owner
-                owner[(v, cols[c])] = c
-    prio = [(orc.fmix32((s + c) ^ seed), s + c) for c in range(m)]
-    start = [orc.fmix32((s + c) ^ seed ^ 0x5BD1E995) % K for c in range(m)]
-    assert list(cols) == _jones_plassmann(ia, ib, prio, start, K)
-    sizes = np.bincount(cols)
-    assert sizes[:K].max() <= 1.3 * m / K
 
 
 def test_contacts_grid_equals_brute_force(orc):
