@@ -1443,6 +1443,12 @@ __global__ __launch_bounds__(kSpreadBS) void k_slot_spread(WP w) {
   if (tid == 0) skip_s = (w.scal[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP)) ? 1 : 0;
   __syncthreads();
   if (skip_s) return;
+  // Partitions whose velocities do not fit the solver's LDS tile gather from
+  // global memory, where the uid order's locality is worth more: they keep it.
+  const int nr = w.part_rep_off[p + 1] - w.part_rep_off[p];
+  const int tile = w.pgs_cfg == 0 ? kPgsCfgReps[0] : (w.pgs_cfg == 1 ? kPgsCfgReps[1]
+                                                     : (w.pgs_cfg == 2 ? kPgsCfgReps[2] : kPgsCfgReps[3]));
+  if (nr > tile) return;
   const int u0 = w.part_copy_off[p], u1 = w.part_copy_off[p + 1];
   const int ncol = w.part_ncol[p];
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
