@@ -147,34 +147,42 @@ __global__ __launch_bounds__(kInfBS) void k_mlp_infer(const uint16_t* __restrict
     for (int o = 0; o < kMlpOut; ++o) Y[(int64_t)(base + l) * kMlpOut + o] = s.y[wv][l * 4 + o];
 }
 
-// world: learned start of every contact copy (uid order in, slot order out)
+// world: learned start of every contact copy (uid order in, slot order out).
+// A persistent grid: every workgroup loads the network into LDS once and then
+// takes tiles of 64 copies (16 per wave) with a grid stride.
+constexpr int kInfWorldBlocks = 2048;
+
 __global__ __launch_bounds__(kInfBS) void k_mlp_world(WP w) {
   __shared__ InferLds s;
+  if (w.scal[SC_FLAGS] != 0) return;
+  const int M = min(w.part_copy_off[w.G], w.Mcap);
+  if (blockIdx.x * 64 >= M) return;
   load_net(s, w.mlp_wb, w.mlp_bias);
   __syncthreads();
-  const int M = min(w.part_copy_off[w.G], w.Mcap);
   const int wv = threadIdx.x >> 6, l = lane_id();
-  const int base = (blockIdx.x * 4 + wv) * 16;
-  if (w.scal[SC_FLAGS] != 0) return;
-  for (int e = l; e < 256; e += 64) {
-    const int r = e >> 4, k = e & 15;
-    const int u = base + r;
-    s.x[wv][e] = (u < M && k < kMlpIn) ? to_bf16(w.r_feat[(int64_t)u * kFeatStride + k]) : 0;
-  }
-  __syncthreads();
-  mlp_tile(s.wb, s.bias, s.x[wv], s.h1[wv], s.h2[wv], s.y[wv]);
-  if (l < 16) {
-    const int u = base + l;
-    if (u < M && w.cp_src[u] >= w.J) {
-      const int slot = w.cp_slot[u];
-      const float sc = w.r_feat[(int64_t)u * kFeatStride + 12];
-      const float mu = w.r_rec[w.Mcap + slot].w;
-      const float ln = fmaxf(s.y[wv][l * 4] * sc, 0.0f);
-      const float bnd = mu * ln;
-      const float l1 = fminf(fmaxf(s.y[wv][l * 4 + 1] * sc, -bnd), bnd);
-      const float l2 = fminf(fmaxf(s.y[wv][l * 4 + 2] * sc, -bnd), bnd);
-      w.r_lamL[slot] = make_float4(ln, l1, l2, 0.0f);
+  for (int tile = blockIdx.x; tile * 64 < M; tile += gridDim.x) {
+    const int base = (tile * 4 + wv) * 16;
+    for (int e = l; e < 256; e += 64) {
+      const int r = e >> 4, k = e & 15;
+      const int u = base + r;
+      s.x[wv][e] = (u < M && k < kMlpIn) ? to_bf16(w.r_feat[(int64_t)u * kFeatStride + k]) : 0;
     }
+    __syncthreads();
+    mlp_tile(s.wb, s.bias, s.x[wv], s.h1[wv], s.h2[wv], s.y[wv]);
+    if (l < 16) {
+      const int u = base + l;
+      if (u < M && w.cp_src[u] >= w.J) {
+        const int slot = w.cp_slot[u];
+        const float sc = w.r_feat[(int64_t)u * kFeatStride + 12];
+        const float mu = w.r_rec[w.Mcap + slot].w;
+        const float ln = fmaxf(s.y[wv][l * 4] * sc, 0.0f);
+        const float bnd = mu * ln;
+        const float l1 = fminf(fmaxf(s.y[wv][l * 4 + 1] * sc, -bnd), bnd);
+        const float l2 = fminf(fmaxf(s.y[wv][l * 4 + 2] * sc, -bnd), bnd);
+        w.r_lamL[slot] = make_float4(ln, l1, l2, 0.0f);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -328,7 +336,7 @@ __global__ void k_mlp_adam(float* __restrict__ params, float* __restrict__ m, fl
 
 hipError_t launch_mlp_world(const WP& w, hipStream_t s) {
   if (w.Mcap <= 0) return hipSuccess;
-  k_mlp_world<<<nblocks(w.Mcap, 64), kInfBS, 0, s>>>(w);
+  k_mlp_world<<<std::min(nblocks(w.Mcap, 64), kInfWorldBlocks), kInfBS, 0, s>>>(w);
   return hipGetLastError();
 }
 
