@@ -111,7 +111,8 @@ __device__ __forceinline__ bool prio_gt(uint32_t ha, int ua, uint32_t hb, int ub
 
 constexpr int kColBS = 1024;
 constexpr int kColWaves = kColBS / 64;
-constexpr int kColLds = 16384;  // partitions with at most this many copies colour in LDS (3 B per copy)
+constexpr int kColLds = 16384;  // partitions with at most this many copies colour in LDS (7 B per copy)
+constexpr int kColRepLds = 8192;  // ... and at most this many replicas (incidence offsets in LDS)
 
 __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   __shared__ int lds_i[kColWaves];
@@ -122,6 +123,8 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   __shared__ int any_s;
   __shared__ signed char col_lds[kColLds];
   __shared__ uint32_t wait_lds[kColLds / 2];  // two 16-bit counters per word
+  __shared__ uint16_t inc_l[2 * kColLds];     // incidence lists: local copy indices
+  __shared__ uint16_t ioff_l[kColRepLds + 1];  // per local replica, into inc_l
   const int p = w.part_order[blockIdx.x];  // largest partitions first
   const int tid = threadIdx.x;
   if (tid == 0) any_s = (w.scal[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP)) ? 1 : 0;
@@ -132,51 +135,89 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   const int nr = r1 - r0;
   if (tid == 0) w.part_nstatic[p] = 0;
   int* inc_cnt = w.inc_off + w.Rcap;  // second half of inc_off holds the counts
-  // incidence lists of the partition's replicas
-  for (int r = tid; r < nr; r += kColBS) inc_cnt[r0 + r] = 0;
-  __syncthreads();
-  for (int u = u0 + tid; u < u1; u += kColBS) {
-    atomicAdd(&inc_cnt[r0 + w.cp_ia[u]], 1);
-    int ib = w.cp_ib[u];
-    if (ib >= 0) atomicAdd(&inc_cnt[r0 + ib], 1);
-  }
-  __syncthreads();
+  // Incidence lists of the partition's replicas: in LDS (16-bit local indices)
+  // when the partition fits, else in global memory.  The per-replica counts
+  // also go to global memory (the conflict-degree feature reads them).
   // The LDS path keeps 16-bit wait counters: every replica must touch fewer
   // than 2^14 copies so that a copy's count stays below 2^15.  Uniform.
-  bool busy = false;
-  for (int r = tid; r < nr; r += kColBS) busy |= inc_cnt[r0 + r] >= (1 << 14);
-  const bool in_lds = u1 - u0 <= kColLds && !__syncthreads_or(busy);
-  for (int u = u0 + tid; u < u1; u += kColBS) {
-    if (in_lds)
-      col_lds[u - u0] = -1;
-    else
-      w.cp_colour[u] = -1;
+  bool in_lds = u1 - u0 <= kColLds && nr <= kColRepLds;
+  if (in_lds) {
+    for (int i = tid; i < (nr + 1) / 2; i += kColBS) wait_lds[i] = 0u;
+    __syncthreads();
+    for (int u = u0 + tid; u < u1; u += kColBS) {
+      const int ia = w.cp_ia[u], ib = w.cp_ib[u];
+      atomicAdd(&wait_lds[ia >> 1], 1u << (16 * (ia & 1)));
+      if (ib >= 0) atomicAdd(&wait_lds[ib >> 1], 1u << (16 * (ib & 1)));
+    }
+    __syncthreads();
+    bool busy = false;
+    for (int r = tid; r < nr; r += kColBS) {
+      const int c = (wait_lds[r >> 1] >> (16 * (r & 1))) & 0xffff;
+      busy |= c >= (1 << 14);
+      inc_cnt[r0 + r] = c;
+    }
+    in_lds = !__syncthreads_or(busy);
   }
-  if (in_lds)
-    for (int i = tid; i < (u1 - u0 + 1) / 2; i += kColBS) wait_lds[i] = 0;
-  __syncthreads();
-  {
-    int carry = 2 * u0;
+  if (in_lds) {
+    int carry = 0;
     for (int base = 0; base < nr; base += kColBS) {
-      int r = base + tid;
-      int v = r < nr ? inc_cnt[r0 + r] : 0;
+      const int r = base + tid;
+      const int v = r < nr ? (wait_lds[r >> 1] >> (16 * (r & 1))) & 0xffff : 0;
       int tot;
-      int pre = block_excl_scan<kColBS>(v, lds_i, tot);
-      if (r < nr) {
-        w.inc_off[r0 + r] = carry + pre;
-        inc_cnt[r0 + r] = 0;
-      }
+      const int pre = block_excl_scan<kColBS>(v, lds_i, tot);
+      if (r < nr) ioff_l[r] = (uint16_t)(carry + pre);
       carry += tot;
     }
+    if (tid == 0) ioff_l[nr] = (uint16_t)carry;
+    __syncthreads();
+    for (int i = tid; i < (nr + 1) / 2; i += kColBS) wait_lds[i] = 0u;
+    __syncthreads();
+    for (int u = u0 + tid; u < u1; u += kColBS) {
+      const int ia = w.cp_ia[u], ib = w.cp_ib[u];
+      const int ka = (atomicAdd(&wait_lds[ia >> 1], 1u << (16 * (ia & 1))) >> (16 * (ia & 1))) & 0xffff;
+      inc_l[ioff_l[ia] + ka] = (uint16_t)(u - u0);
+      if (ib >= 0) {
+        const int kb = (atomicAdd(&wait_lds[ib >> 1], 1u << (16 * (ib & 1))) >> (16 * (ib & 1))) & 0xffff;
+        inc_l[ioff_l[ib] + kb] = (uint16_t)(u - u0);
+      }
+    }
+    __syncthreads();
+    for (int u = u0 + tid; u < u1; u += kColBS) col_lds[u - u0] = -1;
+    for (int i = tid; i < (u1 - u0 + 1) / 2; i += kColBS) wait_lds[i] = 0u;
+    __syncthreads();
+  } else {
+    for (int r = tid; r < nr; r += kColBS) inc_cnt[r0 + r] = 0;
+    __syncthreads();
+    for (int u = u0 + tid; u < u1; u += kColBS) {
+      atomicAdd(&inc_cnt[r0 + w.cp_ia[u]], 1);
+      int ib = w.cp_ib[u];
+      if (ib >= 0) atomicAdd(&inc_cnt[r0 + ib], 1);
+    }
+    __syncthreads();
+    for (int u = u0 + tid; u < u1; u += kColBS) w.cp_colour[u] = -1;
+    {
+      int carry = 2 * u0;
+      for (int base = 0; base < nr; base += kColBS) {
+        int r = base + tid;
+        int v = r < nr ? inc_cnt[r0 + r] : 0;
+        int tot;
+        int pre = block_excl_scan<kColBS>(v, lds_i, tot);
+        if (r < nr) {
+          w.inc_off[r0 + r] = carry + pre;
+          inc_cnt[r0 + r] = 0;
+        }
+        carry += tot;
+      }
+    }
+    __syncthreads();
+    for (int u = u0 + tid; u < u1; u += kColBS) {
+      int ia = r0 + w.cp_ia[u];
+      w.inc[w.inc_off[ia] + atomicAdd(&inc_cnt[ia], 1)] = u;
+      int ib = w.cp_ib[u];
+      if (ib >= 0) w.inc[w.inc_off[r0 + ib] + atomicAdd(&inc_cnt[r0 + ib], 1)] = u;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int u = u0 + tid; u < u1; u += kColBS) {
-    int ia = r0 + w.cp_ia[u];
-    w.inc[w.inc_off[ia] + atomicAdd(&inc_cnt[ia], 1)] = u;
-    int ib = w.cp_ib[u];
-    if (ib >= 0) w.inc[w.inc_off[r0 + ib] + atomicAdd(&inc_cnt[r0 + ib], 1)] = u;
-  }
-  __syncthreads();
   // Jones-Plassmann.  In LDS (the common case): every copy counts its
   // conflicting copies of higher priority; each round colours the copies whose
   // count is zero (an independent set: of two conflicting copies the lower one
@@ -201,12 +242,12 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
       todo |= 1u << j;
       const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
       int n = 0;
-      const int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
+      const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
       for (int e = 0; e < 2; ++e) {
         if (ends[e] < 0) continue;
-        const int k0 = w.inc_off[ends[e]], k1 = k0 + inc_cnt[ends[e]];
-        for (int k = k0; k < k1; ++k) {
-          const int o = w.inc[k];
+        const int k1 = ioff_l[ends[e] + 1];
+        for (int k = ioff_l[ends[e]]; k < k1; ++k) {
+          const int o = u0 + inc_l[k];
           if (o != u && prio_gt(fmix32((uint32_t)o ^ w.seed), o, hu, u)) ++n;
         }
       }
@@ -227,12 +268,12 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
         const uint32_t wv = wait_lds[(u - u0) >> 1] >> (16 * ((u - u0) & 1));
         if ((wv & 0xffffu) != 0) continue;
         uint64_t used = 0;
-        const int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
+        const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
         for (int e = 0; e < 2; ++e) {
           if (ends[e] < 0) continue;
-          const int k0 = w.inc_off[ends[e]], k1 = k0 + inc_cnt[ends[e]];
-          for (int k = k0; k < k1; ++k) {
-            const int co = col_lds[w.inc[k] - u0];
+          const int k1 = ioff_l[ends[e] + 1];
+          for (int k = ioff_l[ends[e]]; k < k1; ++k) {
+            const int co = col_lds[inc_l[k]];
             if (co >= 0) used |= 1ull << co;
           }
         }
@@ -245,12 +286,12 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
         const int j = __ffs(t) - 1;
         const int u = u0 + tid + j * kColBS;
         const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
-        const int ends[2] = {r0 + w.cp_ia[u], w.cp_ib[u] >= 0 ? r0 + w.cp_ib[u] : -1};
+        const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
         for (int e = 0; e < 2; ++e) {
           if (ends[e] < 0) continue;
-          const int k0 = w.inc_off[ends[e]], k1 = k0 + inc_cnt[ends[e]];
-          for (int k = k0; k < k1; ++k) {
-            const int o = w.inc[k];
+          const int k1 = ioff_l[ends[e] + 1];
+          for (int k = ioff_l[ends[e]]; k < k1; ++k) {
+            const int o = u0 + inc_l[k];
             if (o != u && prio_gt(hu, u, fmix32((uint32_t)o ^ w.seed), o))
               atomicSub(&wait_lds[(o - u0) >> 1], 1u << (16 * ((o - u0) & 1)));
           }
