@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
  REP_D, REP_W, PART_COPY_OFF, COPY_KIND, COPY_KEY, COPY_IA, COPY_IB, COPY_COLOUR, COPY_DIR, COPY_RA,
  COPY_RB, COPY_ARR, COPY_BIAS, COPY_MU, COPY_LAMBDA0, COPY_LAMBDA, REP_VT, REP_INVM, REP_INVI, REP_STATE,
  STATE, PART_ITERS, PART_RESID, CACHE_PART, CACHE_KIND, CACHE_KEY, CACHE_VAL, STATS, COPY_FEAT, COPY_LAMBDAL,
- PART_GUARD, PART_RHO0, COPY_DEG) = range(43)
+ PART_GUARD, PART_RHO0, COPY_DEG, REP_CPL) = range(44)
 
 MLP_PARAMS = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 
@@ -46,7 +46,7 @@ _FIELDS = {
     "stats": (STATS, np.float64, 1),
     "copy_feat": (COPY_FEAT, np.float64, 13), "copy_lambdal": (COPY_LAMBDAL, np.float64, 3),
     "part_guard": (PART_GUARD, np.int32, 1), "part_rho0": (PART_RHO0, np.float64, 2),
-    "copy_deg": (COPY_DEG, np.int32, 1),
+    "copy_deg": (COPY_DEG, np.int32, 1), "rep_cpl": (REP_CPL, np.float64, 6),
 }
 
 
@@ -64,7 +64,8 @@ class _Params(C.Structure):
                 ("adaptive", C.c_int32), ("warmstart", C.c_int32), ("halo_k", C.c_int32), ("beta", C.c_int32),
                 ("brute_force_contacts", C.c_int32), ("seed", C.c_uint32), ("learned", C.c_int32),
                 ("mlp", C.c_void_p), ("forced_guard", C.c_void_p), ("lb_masks", C.c_void_p),
-                ("lb_depth", C.c_int32), ("equal_weights", C.c_int32)]
+                ("lb_depth", C.c_int32), ("equal_weights", C.c_int32),
+                ("coupling", C.c_int32)]
 
 
 class _Cache(C.Structure):
@@ -154,7 +155,8 @@ def mlp_infer(params, x12):
 
 DEFAULTS = dict(dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), cfm=0.0, erp=0.2, max_iters=20, tol=1e-4,
                 adaptive=False, warmstart=True, halo_k=1, beta=4, seed=0, brute_force=False, mlp=None,
-                forced_guard=None, lb_masks=None, lb_depth=0, equal_weights=False)
+                forced_guard=None, lb_masks=None, lb_depth=0, equal_weights=False,
+                coupling=False)
 
 
 def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced_iters=None, **kw):
@@ -198,6 +200,7 @@ def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced
     if p["forced_guard"] is not None:
         pr.forced_guard = _ptr(arr(p["forced_guard"], np.int32))
     pr.equal_weights = int(bool(p["equal_weights"]))
+    pr.coupling = int(bool(p["coupling"]))
     if p["lb_masks"] is not None:
         pr.lb_masks = _ptr(arr(p["lb_masks"], np.uint64))
         pr.lb_depth = int(p["lb_depth"])

@@ -642,6 +642,7 @@ typedef struct {
   double x[3], q[4], v[3], w[3];
   double invm, invi[9];
   double vt[6];
+  double cpl[6]; /* coupling impulse of the previous step's cut constraints, as (dv, dw) */
   int32_t body;
 } replica;
 
@@ -1178,6 +1179,133 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
   put(res, ORC_PART_COPY_OFF, pcop, G + 1);
   free(jrng);
   free(crng);
+
+  /* ---- interface coupling (section 7's proposal, optional): the constraints
+   * a partition leaves out because one of their two dynamic bodies is not
+   * active in it still push on the body that is, with the impulse they
+   * received in the previous step.  Per body the incident constraints are
+   * taken in constraint-list order (joints by index, then contacts by key);
+   * the impulse comes from the cache entry of the lowest partition active in
+   * both bodies, converted as the warm start converts it; it acts on the body
+   * inside the partition as F at its lever arm r: dv = F/m, dw = I^-1 (r x F),
+   * with F = -sum_r lambda_r d_r on body a and +sum_r lambda_r d_r on body b
+   * (the signs of the rows' impulses). ---- */
+  for (int64_t r = 0; r < R; ++r)
+    for (int k = 0; k < 6; ++k) rep[r].cpl[k] = 0.0;
+  if (prm->coupling && cache && cache->n > 0) {
+    /* incidence lists: body -> constraints (joints first, then contacts) */
+    int64_t* ioff = (int64_t*)xalloc((size_t)(N + 1) * 8);
+    for (int64_t v = 0; v <= N; ++v) ioff[v] = 0;
+    for (int64_t j = 0; j < sc->n_joints; ++j) {
+      ioff[sc->joint_ab[2 * j] + 1]++;
+      ioff[sc->joint_ab[2 * j + 1] + 1]++;
+    }
+    for (int64_t i = 0; i < C; ++i) {
+      int64_t bc = (int64_t)((cl.c[i].key >> 1) & 0x7fffffff);
+      if (bc >= N) continue;
+      ioff[(cl.c[i].key >> 32) + 1]++;
+      ioff[bc + 1]++;
+    }
+    for (int64_t v = 0; v < N; ++v) ioff[v + 1] += ioff[v];
+    int64_t* ifill = (int64_t*)xalloc((size_t)(N ? N : 1) * 8);
+    int64_t* inc = (int64_t*)xalloc((size_t)(ioff[N] ? ioff[N] : 1) * 8);
+    for (int64_t v = 0; v < N; ++v) ifill[v] = ioff[v];
+    /* entries: joint j as j, contact i as n_joints + i */
+    for (int64_t j = 0; j < sc->n_joints; ++j) {
+      inc[ifill[sc->joint_ab[2 * j]]++] = j;
+      inc[ifill[sc->joint_ab[2 * j + 1]]++] = j;
+    }
+    for (int64_t i = 0; i < C; ++i) {
+      int64_t bc = (int64_t)((cl.c[i].key >> 1) & 0x7fffffff);
+      if (bc >= N) continue;
+      inc[ifill[cl.c[i].key >> 32]++] = sc->n_joints + i;
+      inc[ifill[bc]++] = sc->n_joints + i;
+    }
+    for (int32_t p = 0; p < G; ++p) {
+      int s = 0;
+      while (s < S && !(p >= pbase[s] && p < pbase[s + 1])) ++s;
+      int bit = p - pbase[s];
+      for (int64_t r = prep[p]; r < prep[p + 1]; ++r) {
+        replica* q = &rep[r];
+        int32_t v = q->body;
+        for (int64_t e = ioff[v]; e < ioff[v + 1]; ++e) {
+          int64_t id = inc[e];
+          int kind = id < sc->n_joints ? 0 : 1;
+          int32_t a, b;
+          uint64_t key;
+          const contact* k = NULL;
+          if (kind == 0) {
+            a = sc->joint_ab[2 * id];
+            b = sc->joint_ab[2 * id + 1];
+            key = (uint64_t)id;
+          } else {
+            k = &cl.c[id - sc->n_joints];
+            a = (int32_t)(k->key >> 32);
+            b = (int32_t)((k->key >> 1) & 0x7fffffff);
+            key = k->key;
+          }
+          int32_t o = v == a ? b : a;
+          if (mask[o] >> bit & 1) continue; /* both bodies in P_p: solved here */
+          uint64_t both = mask[v] & mask[o];
+          if (!both) continue;
+          int32_t src = pbase[s] + lowest_bit(both);
+          int64_t f = cache_find(cache, src, kind, key);
+          if (f < 0) continue;
+          const float* val = cache->val + 4 * f;
+          double lam[3], d[9], lever[3];
+          if (kind == 0) {
+            for (int i = 0; i < 3; ++i) lam[i] = val[i];
+            for (int i = 0; i < 9; ++i) d[i] = 0.0;
+            for (int i = 0; i < 3; ++i) d[3 * i + i] = -1.0;
+            const float* an = sc->joint_anchor + 6 * id + (v == a ? 0 : 3);
+            double Rm[9], anc[3] = {an[0], an[1], an[2]};
+            quat_to_mat(q->q, Rm);
+            mat3_vec(Rm, anc, lever);
+          } else {
+            double t1[3], t2[3];
+            orc_tangents(k->n, t1, t2);
+            for (int i = 0; i < 3; ++i) {
+              d[i] = k->n[i];
+              d[3 + i] = t1[i];
+              d[6 + i] = t2[i];
+              lever[i] = v == a ? k->ra[i] : k->rb[i];
+            }
+            double mu = sc->mu[s];
+            double ln = val[0] > 0.0f ? (double)val[0] : 0.0;
+            double fw[3] = {val[1], val[2], val[3]};
+            lam[0] = ln;
+            lam[1] = clampd(dot3(fw, t1), -mu * ln, mu * ln);
+            lam[2] = clampd(dot3(fw, t2), -mu * ln, mu * ln);
+          }
+          double F[3], tq[3], dw[3];
+          for (int i = 0; i < 3; ++i) F[i] = lam[0] * d[i] + lam[1] * d[3 + i] + lam[2] * d[6 + i];
+          if (v == a)
+            for (int i = 0; i < 3; ++i) F[i] = -F[i];
+          cross3(lever, F, tq);
+          mat3_vec(q->invi, tq, dw);
+          for (int i = 0; i < 3; ++i) {
+            q->cpl[i] += q->invm * F[i];
+            q->cpl[3 + i] += dw[i];
+          }
+        }
+        for (int i = 0; i < 3; ++i) {
+          q->v[i] += q->cpl[i];
+          q->w[i] += q->cpl[3 + i];
+          q->vt[i] = q->v[i];
+          q->vt[3 + i] = q->w[i];
+        }
+      }
+    }
+    free(ioff);
+    free(ifill);
+    free(inc);
+  }
+  {
+    double* cpl = (double*)xalloc((size_t)(R ? R : 1) * 48);
+    for (int64_t r = 0; r < R; ++r)
+      for (int k = 0; k < 6; ++k) cpl[6 * r + k] = rep[r].cpl[k];
+    put(res, ORC_REP_CPL, cpl, 6 * R);
+  }
 
   /* ---- rows (Eq. 1-7): three rows per copy.
    * contact: directions n, t1, t2; the normal row has lower bound 0, the two

@@ -56,6 +56,15 @@ typedef struct {
   /* 1: every overlap body blends its replicas with equal weights 1/|W|, the
    * naive choice section 5.3 compares the geodesic weights against */
   int32_t equal_weights;
+  /* 1: interface coupling by the previous step's constraint impulses (the
+   * coupling section 7 proposes, after [BW97]).  A constraint of the step
+   * between two dynamic bodies with exactly one of them active in partition i
+   * is cut from that partition's solve; its impulse of the previous step, as
+   * the partition with the lowest id among those active in both bodies left
+   * it (cache key as for the warm start, friction carried as a world vector,
+   * projected and clipped as the warm start does), acts on the body inside
+   * P_i as a fixed impulse added to its free velocity before the solve. */
+  int32_t coupling;
 } orc_params;
 
 #define ORC_MLP_IN 12
@@ -118,6 +127,7 @@ enum orc_field {
   ORC_PART_GUARD,        /* i32 [G] 1 when the learned start was kept */
   ORC_PART_RHO0,         /* f64 [G*2] initial residual of the plain and of the learned start */
   ORC_COPY_DEG,          /* i32 [M] conflict degree */
+  ORC_REP_CPL,           /* f64 [R*6] interface-coupling impulse per replica (dv, dw); zeros without coupling */
   ORC_NFIELDS
 };
 
