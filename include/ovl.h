@@ -79,6 +79,20 @@ enum { OVL_WARM_NONE = 0, OVL_WARM_PLAIN = 1, OVL_WARM_LEARNED = 2 };
 /* Blend weights of the overlap bodies: geodesic (section 5.3, Eq. 15-16,
  * Alg. 5) or equal 1/|W| (the naive weights section 5.3 compares against). */
 enum { OVL_WEIGHTS_GEODESIC = 0, OVL_WEIGHTS_EQUAL = 1 };
+/* Interface coupling between partitions (section 7 names it as a way to
+ * couple the workers' solutions beyond the overlap, after [BW97]).
+ * OVL_COUPLING_PREV_IMPULSE: a constraint of the step between two dynamic
+ * bodies of which only one is active in partition i is left out of i's solve
+ * (section 4); with this option its impulse of the previous step still acts
+ * on the body inside i, as a fixed impulse added to the body's free velocity
+ * v + h M^-1 f before the warm start and the sweeps.  The impulse is the one
+ * the constraint left, at the end of the previous step, in the partition
+ * with the lowest id among those active in both of its bodies (found by the
+ * warm start's key; a contact's friction is carried as a world vector,
+ * projected on the new tangents and clipped to the new friction box, its
+ * normal impulse clamped to >= 0); none if that partition did not solve it
+ * then.  The features of the learned warm start see the coupled velocity. */
+enum { OVL_COUPLING_NONE = 0, OVL_COUPLING_PREV_IMPULSE = 1 };
 
 /* Parameters of the warm-start network 12 -> 64 -> 64 -> 3 (ReLU), flat:
  * W1[12][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3], input index first. */
@@ -100,6 +114,7 @@ typedef struct {
   int32_t warmstart;  /* OVL_WARM_* */
   uint32_t seed;      /* colouring priority seed */
   int32_t weights;    /* OVL_WEIGHTS_* */
+  int32_t coupling;   /* OVL_COUPLING_* */
 } ovl_params;
 
 /* Device context: the stream every kernel runs on (NULL = the null stream)
@@ -270,6 +285,7 @@ enum {
   OVL_DBG_COPY_LAMBDAL,   /* f32 [M*3] learned start, uid order (learned mode) */
   OVL_DBG_PART_GUARD,     /* i32 [G] 1 when the learned start was kept */
   OVL_DBG_PART_RHO0,      /* f32 [G*2] initial residual of the plain and the learned start */
+  OVL_DBG_REP_CPL,        /* f32 [R*6] interface-coupling impulse per replica (dv, dw), partition-major */
   OVL_DBG_NFIELDS
 };
 ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int64_t capacity_bytes, int64_t* count);

@@ -23,18 +23,20 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_NONFINITE, ERR_DEVICE, NOT_CONVE
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "NONFINITE", 5: "DEVICE", 6: "NOT_CONVERGED"}
 MODE_FIXED, MODE_ADAPTIVE = 0, 1
 WEIGHTS_GEODESIC, WEIGHTS_EQUAL = 0, 1
+COUPLING_NONE, COUPLING_PREV_IMPULSE = 0, 1
 WARM_NONE, WARM_PLAIN, WARM_LEARNED = 0, 1, 2
 MLP_PARAMS = 5187
 
 DBG_FIELDS = ["contact_key", "contact_geom", "adj_off", "adj", "mask", "part_rep_off", "rep_body", "rep_d", "rep_w",
               "part_copy_off", "copy_kind", "copy_key", "copy_ia", "copy_ib", "copy_colour", "copy_lambda0",
               "copy_lambda", "rep_state", "part_iters", "part_resid", "cache_part", "cache_kind", "cache_key",
-              "cache_val", "part_col_off", "copy_feat", "copy_lambdal", "part_guard", "part_rho0"]
+              "cache_val", "part_col_off", "copy_feat", "copy_lambdal", "part_guard", "part_rho0", "rep_cpl"]
 _DBG_DTYPE = {"contact_key": (np.uint64, 1), "contact_geom": (np.float32, 8), "mask": (np.uint64, 1),
               "rep_w": (np.float32, 1), "copy_key": (np.uint64, 1), "copy_lambda0": (np.float32, 3),
               "copy_lambda": (np.float32, 3), "rep_state": (np.float32, 13), "part_resid": (np.float32, 1),
               "cache_key": (np.uint64, 1), "cache_val": (np.float32, 4), "copy_feat": (np.float32, 13),
-              "copy_lambdal": (np.float32, 3), "part_rho0": (np.float32, 2)}
+              "copy_lambdal": (np.float32, 3), "part_rho0": (np.float32, 2),
+              "rep_cpl": (np.float32, 6)}
 
 
 class OvlError(RuntimeError):
@@ -55,7 +57,7 @@ class ovl_world_desc(C.Structure):
 class ovl_params(C.Structure):
     _fields_ = [("dt", C.c_float), ("gravity", C.c_float * 3), ("cfm", C.c_float), ("erp", C.c_float),
                 ("tol", C.c_float), ("max_iters", C.c_int32), ("mode", C.c_int32), ("warmstart", C.c_int32),
-                ("seed", C.c_uint32), ("weights", C.c_int32)]
+                ("seed", C.c_uint32), ("weights", C.c_int32), ("coupling", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -172,13 +174,15 @@ def _p(a):
 
 
 def make_params(dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), cfm=0.0, erp=0.2, tol=1e-4, max_iters=20,
-                mode=MODE_FIXED, warmstart=WARM_PLAIN, seed=0, weights=WEIGHTS_GEODESIC) -> ovl_params:
+                mode=MODE_FIXED, warmstart=WARM_PLAIN, seed=0, weights=WEIGHTS_GEODESIC,
+                coupling=COUPLING_NONE) -> ovl_params:
     p = ovl_params()
     p.dt = dt
     p.gravity[0], p.gravity[1], p.gravity[2] = gravity
     p.cfm, p.erp, p.tol = cfm, erp, tol
     p.max_iters, p.mode, p.warmstart, p.seed = int(max_iters), int(mode), int(warmstart), int(seed) & 0xFFFFFFFF
     p.weights = int(weights)
+    p.coupling = int(coupling)
     return p
 
 

@@ -188,7 +188,6 @@ __device__ void grow(const LbMem& L, int* load, int* tail, int n, int root, uint
 
 // Alg. 6 for one contact, by the whole wavefront (a, b uniform)
 __device__ void apply_rule(const LbMem& L, int* load, int* tail, int n, int depth, int a, int b) {
-  const int lane = lane_id();
   const uint64_t WA = L.m[a], WB = L.m[b];
   if ((WA & WB) == 0ull) {
     // Figure 9 (i), (ii): the lighter side becomes aware of the other body

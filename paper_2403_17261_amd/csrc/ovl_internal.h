@@ -61,6 +61,7 @@ struct WP {
   float dt, gx, gy, gz, cfm, erp, tol;
   int32_t max_iters, adaptive, warmstart, halo_k, beta;
   int32_t equal_w;               // 1: equal blend weights instead of geodesic ones
+  int32_t couple;                // 1: previous-step impulses of cut constraints act on the partition's bodies
   uint32_t seed;
   int32_t forced;                // 1: part_force_iters holds each partition's sweep count
   // static body data
@@ -86,6 +87,8 @@ struct WP {
   const float* j_anchor;        // [J*6]
   const int32_t* jadj_off;      // [N+1] joint partners per body, sorted
   const int32_t* jadj;
+  const int32_t* jinc_off;      // [N+1] joints of each body, by joint index
+  const int32_t* jinc;
   // partitions
   const int32_t* owner_local;   // [N] owner - base of the body's scene
   const int32_t* part_force_iters;  // [G]
@@ -157,6 +160,7 @@ struct WP {
   float4* r_gen;                // [2][Mcap] (only with capsules)
   int2* r_ids;                  // [Mcap] (local replica a | kJointFlag | kGenFlag, local replica b or -1)
   float4* rep_ax;               // [Rcap] capsule axis u and 1/I_axis - 1/I_perp of each replica
+  float4* rep_cpl;              // [2*Rcap] interface-coupling impulse per replica: (dv, 0), then (dw, 0)
   float4* r_lam;                // [Mcap] impulses (3 used)
   float4* r_lam0;               // [Mcap] warm-start impulses
   float4* rep_v4;               // [2*Rcap] velocity storage of partitions too large for LDS

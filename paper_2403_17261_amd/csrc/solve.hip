@@ -18,6 +18,10 @@
 //  * Warm start: the previous step's impulses of the same
 //    (partition, kind, key); friction is carried as a world vector, projected
 //    on the new tangents and clipped to the new box.
+//  * Interface coupling (optional, section 7's proposal after [BW97]): a
+//    constraint left out of a partition because one of its dynamic bodies is
+//    not active there still pushes the body that is, with its impulse of the
+//    previous step, added to that replica's free velocity.
 //  * Gauss-Seidel: one workgroup per partition (the paper's worker); replica
 //    velocities and inverse masses stay in LDS; colours are separated by
 //    workgroup barriers.  Adaptive mode stops when a sweep's largest
@@ -405,6 +409,115 @@ __device__ __forceinline__ int cache_find(const WP& w, int n, int part, int kind
   return -1;
 }
 
+// ----------------------------------------------------- interface coupling ----
+// One thread per body v.  For each partition i that v is active in and one of
+// v's constraint-graph neighbours is not, the constraints of v whose other
+// body is outside P_i are cut from i's solve.  Each one's impulse of the
+// previous step (cache entry of the lowest partition active in both bodies,
+// converted as the warm start converts it) acts on v as F at v's lever arm:
+// dv = F/m, dw = I^-1 (r x F), F = -sum_r lambda_r d_r on body a and
+// +sum_r lambda_r d_r on body b.  Summed per replica in constraint-list order
+// (joints by index, then contacts by key: those where v is body b come first,
+// their body a being smaller) into rep_cpl.
+__device__ __forceinline__ void couple_add(const WP& w, int v, f3 F, f3 r, f3& dv, f3& dw) {
+  const float im = w.b_invm[v], ii = w.b_invI[v];
+  const f3 u = w.has_caps ? body_axis(w, v) : mk(0.0f, 0.0f, 1.0f);
+  const float dI = w.has_caps ? w.b_dI[v] : 0.0f;
+  dv = add(dv, scale(F, im));
+  dw = add(dw, inv_inertia(ii, u, dI, cross(r, F)));
+}
+
+__device__ __forceinline__ void couple_contact(const WP& w, int prevM, int pb, uint64_t mv, int v, int c, f3& dv,
+                                               f3& dw) {
+  const int64_t MC = w.Mcap, CC = w.Ccap;
+  const int a = w.c_a[c];
+  const uint32_t bk = w.c_bkey[c];
+  const int b = (int)(bk >> 1);
+  const int o = a == v ? b : a;
+  const uint64_t both = mv & w.mask[o];
+  if (!both) return;
+  const int hit = cache_find(w, prevM, pb + __builtin_ctzll(both), 1, ((uint64_t)a << 32) | bk);
+  if (hit < 0) return;
+  const f3 n = mk(w.c_geom[c], w.c_geom[CC + c], w.c_geom[2 * CC + c]);
+  f3 t1, t2;
+  tangents(n, t1, t2);
+  const float ln = fmaxf(w.wc_val[hit], 0.0f);
+  const f3 fw = mk(w.wc_val[MC + hit], w.wc_val[2 * MC + hit], w.wc_val[3 * MC + hit]);
+  const float bnd = w.s_mu[w.b_scene[a]] * ln;
+  const float l1 = fminf(fmaxf(dot(fw, t1), -bnd), bnd);
+  const float l2 = fminf(fmaxf(dot(fw, t2), -bnd), bnd);
+  const f3 P = add(add(scale(n, ln), scale(t1, l1)), scale(t2, l2));
+  f3 ra, rb;
+  contact_arms(w, c, a, b, n, ra, rb);
+  if (a == v)
+    couple_add(w, v, scale(P, -1.0f), ra, dv, dw);
+  else
+    couple_add(w, v, P, rb, dv, dw);
+}
+
+__global__ void k_couple(WP w) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= w.N || step_failed(w)) return;
+  const int N = w.N;
+  const uint64_t m = w.mask[v];
+  const int n = __popcll(m);
+  const int bm0 = w.rep_off_bm[v];
+  const int64_t RC = w.Rcap;
+  for (int k = 0; k < n; ++k) {
+    const int r = w.rep_pm_of_bm[bm0 + k];
+    w.rep_cpl[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    w.rep_cpl[RC + r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  const int prevM = w.scal[SC_PREV_NCOPY];
+  if (prevM <= 0 || w.adj_off[N] > w.Acap) return;
+  const int a0 = w.adj_off[v], a1 = w.adj_off[v + 1];
+  uint64_t cut = 0;
+  for (int k = a0; k < a1; ++k) {
+    const int u = w.adj[k];
+    if (u >= 0) cut |= m & ~w.mask[u];
+  }
+  if (!cut) return;
+  const int pb = w.s_part_base[w.b_scene[v]];
+  for (uint64_t bits = cut; bits; bits &= bits - 1) {
+    const int i = __builtin_ctzll(bits);
+    f3 dv = mk(0.0f, 0.0f, 0.0f), dw = mk(0.0f, 0.0f, 0.0f);
+    // ball joints (rows along -e_k: the impulse on body a is +lambda)
+    for (int e = w.jinc_off[v]; e < w.jinc_off[v + 1]; ++e) {
+      const int j = w.jinc[e];
+      const int ja = w.j_ab[2 * j], jb = w.j_ab[2 * j + 1];
+      const int o = ja == v ? jb : ja;
+      if (w.mask[o] >> i & 1) continue;
+      const uint64_t both = m & w.mask[o];
+      if (!both) continue;
+      const int hit = cache_find(w, prevM, pb + __builtin_ctzll(both), 0, (uint64_t)j);
+      if (hit < 0) continue;
+      const int64_t MC = w.Mcap;
+      const f3 lam = mk(w.wc_val[hit], w.wc_val[MC + hit], w.wc_val[2 * MC + hit]);
+      const float* an = w.j_anchor + 6 * j + (ja == v ? 0 : 3);
+      const f3 r = quat_rotate(w.st[3 * N + v], w.st[4 * N + v], w.st[5 * N + v], w.st[6 * N + v],
+                               mk(an[0], an[1], an[2]));
+      couple_add(w, v, ja == v ? lam : scale(lam, -1.0f), r, dv, dw);
+    }
+    // contacts whose body a is a smaller neighbour u (adjacency is sorted, -1 padded)
+    for (int k = a0; k < a1; ++k) {
+      const int u = w.adj[k];
+      if (u < 0 || u >= v) break;
+      if (w.mask[u] >> i & 1) continue;
+      for (int c = w.coff[u]; c < w.coff[u + 1]; ++c)
+        if ((w.c_bkey[c] >> 1) == (uint32_t)v) couple_contact(w, prevM, pb, m, v, c, dv, dw);
+    }
+    // contacts whose body a is v
+    for (int c = w.coff[v]; c < w.coff[v + 1]; ++c) {
+      const uint32_t o = w.c_bkey[c] >> 1;
+      if (o >= (uint32_t)N || (w.mask[o] >> i & 1)) continue;
+      couple_contact(w, prevM, pb, m, v, c, dv, dw);
+    }
+    const int r = w.rep_pm_of_bm[bm0 + __popcll(m & ((1ull << i) - 1))];
+    w.rep_cpl[r] = make_float4(dv.x, dv.y, dv.z, 0.0f);
+    w.rep_cpl[RC + r] = make_float4(dw.x, dw.y, dw.z, 0.0f);
+  }
+}
+
 // Features of a contact copy for the learned warm start (joints: zeros).
 // Velocities are those at the start of the solve (v~ = v + h g); the velocity
 // scale is g h and the impulse scale s = g h / (1/m_a + 1/m_b):
@@ -431,15 +544,26 @@ __device__ void write_features(const WP& w, int u, int src, int p, float l0, flo
   tangents(n, t1, t2);
   const float h = w.dt;
   const f3 hg = mk(h * w.gx, h * w.gy, h * w.gz);
-  const f3 va = add(mk(w.st[7 * N + a], w.st[8 * N + a], w.st[9 * N + a]), hg);
-  const f3 wa = mk(w.st[10 * N + a], w.st[11 * N + a], w.st[12 * N + a]);
+  const int r0 = w.part_rep_off[p];
+  f3 va = add(mk(w.st[7 * N + a], w.st[8 * N + a], w.st[9 * N + a]), hg);
+  f3 wa = mk(w.st[10 * N + a], w.st[11 * N + a], w.st[12 * N + a]);
+  if (w.couple) {
+    const float4 cv = w.rep_cpl[r0 + w.cp_ia[u]], cw = w.rep_cpl[w.Rcap + r0 + w.cp_ia[u]];
+    va = add(va, mk(cv.x, cv.y, cv.z));
+    wa = add(wa, mk(cw.x, cw.y, cw.z));
+  }
   f3 pa = add(va, cross(wa, ra));
   f3 pb = mk(0, 0, 0);
   const float ima = w.b_invm[a];
   float imb = 0.0f;
   if (b >= 0) {
-    const f3 vb = add(mk(w.st[7 * N + b], w.st[8 * N + b], w.st[9 * N + b]), hg);
-    const f3 wb = mk(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b]);
+    f3 vb = add(mk(w.st[7 * N + b], w.st[8 * N + b], w.st[9 * N + b]), hg);
+    f3 wb = mk(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b]);
+    if (w.couple) {
+      const float4 cv = w.rep_cpl[r0 + w.cp_ib[u]], cw = w.rep_cpl[w.Rcap + r0 + w.cp_ib[u]];
+      vb = add(vb, mk(cv.x, cv.y, cv.z));
+      wb = add(wb, mk(cw.x, cw.y, cw.z));
+    }
     pb = add(vb, cross(wb, rb));
     imb = w.b_invm[b];
   }
@@ -449,7 +573,6 @@ __device__ void write_features(const WP& w, int u, int src, int p, float l0, flo
   const float sim = vs / (ima + imb);
   const float margin = w.s_margin[w.b_scene[a]];
   const int* inc_cnt = w.inc_off + w.Rcap;
-  const int r0 = w.part_rep_off[p];
   int deg = inc_cnt[r0 + w.cp_ia[u]] - 1;
   if (b >= 0) deg += inc_cnt[r0 + w.cp_ib[u]] - 1;
   f[0] = n.x;
@@ -850,15 +973,27 @@ __device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, i
   if (solve) w.r_lam[slot] = R.lam;
 }
 
-// replica velocities with gravity applied (v~ = v + h g) and inverse masses
+// replica velocities with gravity applied (v~ = v + h g), plus the interface
+// coupling impulse when that option is on, and inverse masses
 template <int BS>
 __device__ void load_replicas(const WP& w, Vel V, int r0, int nr) {
   const int N = w.N;
   const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
   for (int r = threadIdx.x; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
-    V.p[r] = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
-    V.p[r + V.stride] = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
+    float4 lin = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
+    float4 ang = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
+    if (w.couple) {
+      const float4 cv = w.rep_cpl[r0 + r], cw = w.rep_cpl[w.Rcap + r0 + r];
+      lin.x += cv.x;
+      lin.y += cv.y;
+      lin.z += cv.z;
+      ang.x += cw.x;
+      ang.y += cw.y;
+      ang.z += cw.z;
+    }
+    V.p[r] = lin;
+    V.p[r + V.stride] = ang;
   }
 }
 
@@ -1556,6 +1691,10 @@ __global__ __launch_bounds__(kSpreadBS) void k_slot_spread(WP w) {
 
 hipError_t launch_solve_pre(const WP& w, hipStream_t s) {
   hipError_t e;
+  if (w.couple && w.N > 0) {
+    k_couple<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+  }
   if (w.G > 0) {
     k_part_order<<<nblocks(w.G, kOrderBS), kOrderBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;

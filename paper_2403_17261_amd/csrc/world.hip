@@ -159,6 +159,7 @@ struct ovl_world {
     w.r_rec = alloc<float4>(g, (size_t)3 * Mcap, ok);
     w.r_gen = alloc<float4>(g, w.has_caps ? (size_t)2 * Mcap : 1, ok);
     w.rep_ax = alloc<float4>(g, w.has_caps ? (size_t)Rcap : 1, ok);
+    w.rep_cpl = alloc<float4>(g, (size_t)2 * Rcap, ok);
     w.r_ids = alloc<int2>(g, Mcap, ok);
     w.r_lam = alloc<float4>(g, Mcap, ok);
     w.r_lam0 = alloc<float4>(g, Mcap, ok);
@@ -234,6 +235,7 @@ struct ovl_world {
     wp.warmstart = p.warmstart == OVL_WARM_PLAIN;
     wp.seed = p.seed;
     wp.equal_w = p.weights == OVL_WEIGHTS_EQUAL ? 1 : 0;
+    wp.couple = p.coupling == OVL_COUPLING_PREV_IMPULSE ? 1 : 0;
   }
 
   bool read_scal(int32_t* out) {
@@ -365,6 +367,7 @@ ovl_status validate_params(const ovl_params* p, std::string& err) {
   else if (p->warmstart != OVL_WARM_NONE && p->warmstart != OVL_WARM_PLAIN) err = "bad warmstart mode";
   else if (!(p->tol >= 0.0f)) err = "tol must be >= 0";
   else if (p->weights != OVL_WEIGHTS_GEODESIC && p->weights != OVL_WEIGHTS_EQUAL) err = "bad weights mode";
+  else if (p->coupling != OVL_COUPLING_NONE && p->coupling != OVL_COUPLING_PREV_IMPULSE) err = "bad coupling mode";
   else if (!std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2]))
     err = "gravity must be finite";
   else
@@ -483,7 +486,7 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   if (d->plane_off[0] != 0 || d->ssph_off[0] != 0) return bad("plane_off[0] and ssph_off[0] must be 0");
   const int P = d->plane_off[S], Q = d->ssph_off[S];
   if ((P > 0 && !d->planes) || (Q > 0 && !d->ssph)) return bad("static arrays must not be NULL");
-  std::vector<std::vector<int32_t>> jad(N);
+  std::vector<std::vector<int32_t>> jad(N), jin(N);
   for (int j = 0; j < J; ++j) {
     int a = d->joint_ab[2 * j], b = d->joint_ab[2 * j + 1];
     if (a < 0 || a >= N || b < 0 || b >= N || a == b) return bad("joint body index out of range");
@@ -492,6 +495,8 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
     joint_off[d->scene[a] + 1]++;
     jad[a].push_back(b);
     jad[b].push_back(a);
+    jin[a].push_back(j);
+    jin[b].push_back(j);
   }
   for (int s = 0; s < S; ++s) joint_off[s + 1] += joint_off[s];
   std::vector<int32_t> jadj_off(N + 1, 0), jadj;
@@ -499,6 +504,11 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
     std::sort(jad[i].begin(), jad[i].end());
     jadj_off[i + 1] = jadj_off[i] + (int32_t)jad[i].size();
     jadj.insert(jadj.end(), jad[i].begin(), jad[i].end());
+  }
+  std::vector<int32_t> jinc_off(N + 1, 0), jinc;
+  for (int i = 0; i < N; ++i) {
+    jinc_off[i + 1] = jinc_off[i] + (int32_t)jin[i].size();
+    jinc.insert(jinc.end(), jin[i].begin(), jin[i].end());
   }
 
   ovl_world* w = new ovl_world();
@@ -552,6 +562,8 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   float* j_anchor = w->alloc<float>(g, 6 * (size_t)std::max(J, 1), ok);
   int32_t* jadj_off_d = w->alloc<int32_t>(g, N + 1, ok);
   int32_t* jadj_d = w->alloc<int32_t>(g, std::max<size_t>(jadj.size(), 1), ok);
+  int32_t* jinc_off_d = w->alloc<int32_t>(g, N + 1, ok);
+  int32_t* jinc_d = w->alloc<int32_t>(g, std::max<size_t>(jinc.size(), 1), ok);
   wp.joint_viol = w->alloc<float>(g, std::max(J, 1), ok);
   wp.owner_local = w->alloc<int32_t>(g, Np, ok);
   wp.st = w->alloc<float>(g, (size_t)13 * Np, ok);
@@ -623,6 +635,8 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   wp.j_anchor = j_anchor;
   wp.jadj_off = jadj_off_d;
   wp.jadj = jadj_d;
+  wp.jinc_off = jinc_off_d;
+  wp.jinc = jinc_d;
   std::vector<int32_t> zeros(SC_COUNT, 0);
   std::vector<int64_t> zeros64(8, 0);
   ok = w->upload(b_scene, d->scene, N * sizeof(int32_t)) && w->upload(b_radius, d->radius, N * sizeof(float)) &&
@@ -639,6 +653,8 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
        w->upload(j_anchor, d->joint_anchor, (size_t)6 * J * sizeof(float)) &&
        w->upload(jadj_off_d, jadj_off.data(), (N + 1) * sizeof(int32_t)) &&
        w->upload(jadj_d, jadj.data(), jadj.size() * sizeof(int32_t)) &&
+       w->upload(jinc_off_d, jinc_off.data(), (N + 1) * sizeof(int32_t)) &&
+       w->upload(jinc_d, jinc.data(), jinc.size() * sizeof(int32_t)) &&
        w->upload(wp.st, st_cols.data(), (size_t)13 * N * sizeof(float)) &&
        w->upload(wp.scal, zeros.data(), SC_COUNT * sizeof(int32_t)) &&
        w->upload(wp.stat_i64, zeros64.data(), 8 * sizeof(int64_t));
@@ -1390,6 +1406,18 @@ extern "C" ovl_status ovl_read_debug(ovl_world* w, int32_t field, void* dst, int
       std::vector<int32_t> v;
       ok = dl(w, v, p.part_guard, G);
       put(v.data(), G, 4);
+      break;
+    }
+    case OVL_DBG_REP_CPL: {
+      std::vector<float4> rc;
+      ok = dl(w, rc, p.rep_cpl, (size_t)2 * p.Rcap);
+      std::vector<float> o((size_t)6 * R);
+      for (int r = 0; r < R && ok; ++r) {
+        const float4 a = rc[r], b = rc[(size_t)p.Rcap + r];
+        const float v[6] = {a.x, a.y, a.z, b.x, b.y, b.z};
+        for (int k = 0; k < 6; ++k) o[6 * (size_t)r + k] = v[k];
+      }
+      put(o.data(), (size_t)6 * R, 4);
       break;
     }
     case OVL_DBG_PART_RHO0: {

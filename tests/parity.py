@@ -33,7 +33,7 @@ def oracle_kwargs(sc, params, halo_k, beta):
     return dict(dt=params.dt, gravity=tuple(params.gravity), cfm=params.cfm, erp=params.erp,
                 max_iters=params.max_iters, tol=params.tol, adaptive=params.mode == 1,
                 warmstart=params.warmstart == 1, seed=params.seed, halo_k=halo_k, beta=beta,
-                equal_weights=params.weights == 1)
+                equal_weights=params.weights == 1, coupling=params.coupling == 1)
 
 
 def check_state(sc, gpu, ref, dt, label=""):
@@ -68,7 +68,7 @@ def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, fo
     owner = sc.owner if owner is None else owner
     pps = sc.parts_per_scene if pps is None else pps
     s0 = w.read_state()
-    cache = w.cache() if params.warmstart else None
+    cache = w.cache() if params.warmstart or params.coupling else None
     if forced is not None:
         w.force_iters(forced)
     stats = w.step(1, stats=True)
@@ -102,6 +102,15 @@ def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, fo
             log(f"  warm start: {len(bad)} copies beyond {1e-5 * scale:.3e}; first uid {u} kind {g['copy_kind'][u]} "
                 f"key {int(g['copy_key'][u]):#x} gpu {g['copy_lambda0'][u]} oracle {o['copy_lambda0'][u]}")
         assert d0 <= 1e-5 * scale, f"warm start differs by {d0}"
+    if params.coupling:
+        # interface-coupling impulses per replica: float32 sums of a few
+        # float32 impulses against the oracle's double ones
+        gc, oc = w.debug("rep_cpl").astype(np.float64), o["rep_cpl"]
+        scale = max(np.abs(oc).max(initial=0.0), G_ACC * params.dt)
+        dc = np.abs(gc - oc).max(initial=0.0)
+        log(f"  {label} coupled replicas {int((np.abs(oc).max(axis=1) > 0).sum())}, largest impulse {scale:.3e}, "
+            f"worst difference {dc:.2e}")
+        assert dc <= 1e-5 * scale, f"coupling impulses differ by {dc}"
     if forced is None and not params.mode:
         assert np.all(g["part_iters"] == params.max_iters)
     check_state(sc, gs, o["state"], params.dt, label)
