@@ -13,15 +13,17 @@ every 10 steps, 2-hop overlap), 1000 steps.
 
 --workload bowl-lb: the paper's Bowl scene with dynamic load balancing
 (section 5.4): 5,040 spheres dropped into the bowl, 7 workers starting from
-the naive division of the body list, growth depth 0, worker sets updated from
-every step's new contacts; first 600 steps.  Also reports the per-worker body
+the naive division of the body list, growth depth 0, worker sets updated
+with every contact of the step; first 600 steps.  Also reports the per-worker body
 and contact distributions over the run and the same run without balancing.
 
 --workload accuracy: the accuracy study on the 51,200-link chains (256
 chains of 200 ball-jointed spheres over 16 static spheres, 16 x-slabs, h
 1/120 s, 40 sweeps, 500 steps): overlap depth k = 1..4 (gamma = k - 1) with
-geodesic and with equal blend weights, and one partition as the reference;
-joint violation and total residual sampled every 25 steps.
+geodesic and with equal blend weights, with geodesic weights plus interface
+coupling by the previous step's impulses of cut constraints (section 7), and
+one partition as the reference; joint violation and total residual sampled
+every 25 steps.
 
 --workload batched: 512 independent bowl scenes (log-uniform 200..5000
 spheres, 1..6 k-means partitions each, fixed at the start), 30 sweeps per
@@ -313,10 +315,13 @@ def bench_accuracy(args):
     steps = args.steps or sc.steps
     every = 25
     runs = []
-    variants = [(k, wmode) for k in (1, 2, 3, 4) for wmode in ("geodesic", "equal")] + [(0, "one partition")]
-    for k, wmode in variants:
+    # (overlap depth k, blend weights, interface coupling); k = 0: one partition
+    variants = ([(k, wmode, False) for k in (1, 2, 3, 4) for wmode in ("geodesic", "equal")] +
+                [(k, "geodesic", True) for k in (1, 2, 3, 4)] + [(0, "one partition", False)])
+    for k, wmode, cpl in variants:
         p = ovl.make_params(dt=sc.dt, max_iters=sc.iters, mode=ovl.MODE_FIXED, warmstart=ovl.WARM_PLAIN,
-                            weights=ovl.WEIGHTS_EQUAL if wmode == "equal" else ovl.WEIGHTS_GEODESIC)
+                            weights=ovl.WEIGHTS_EQUAL if wmode == "equal" else ovl.WEIGHTS_GEODESIC,
+                            coupling=ovl.COUPLING_PREV_IMPULSE if cpl else ovl.COUPLING_NONE)
         w = ovl.World(sc, p)
         if k == 0:
             w.set_partitions(np.zeros(sc.n_bodies, np.int32), np.array([1], np.int32), halo_k=1, beta=sc.beta)
@@ -335,7 +340,8 @@ def bench_accuracy(args):
         w.close()
         a = np.array(samples, np.float64)
         half = a[len(a) // 2:]
-        r = {"k": k, "weights": wmode, "ms_per_step": 1e3 * secs / steps,
+        r = {"k": k, "weights": wmode, "coupling": "previous-step impulses" if cpl else "none",
+             "ms_per_step": 1e3 * secs / steps,
              "joint_violation_sum_mean_second_half": float(half[:, 2].mean()),
              "joint_violation_max_mean_second_half": float(half[:, 1].mean()),
              "joint_violation_max_worst": float(a[:, 1].max()),
@@ -343,11 +349,11 @@ def bench_accuracy(args):
              "overlap_bodies_mean": float(a[:, 5].mean()), "replicas_mean": float(a[:, 6].mean()),
              "series": [[int(x[0]), round(float(x[2]), 6), round(float(x[3]), 4)] for x in a]}
         runs.append(r)
-        log(f"[accuracy k={k} {wmode}] joint violation sum {r['joint_violation_sum_mean_second_half']:.4e} m "
+        log(f"[accuracy k={k} {wmode}{' coupled' if cpl else ''}] joint violation sum {r['joint_violation_sum_mean_second_half']:.4e} m "
             f"(max {r['joint_violation_max_mean_second_half']:.3e}), total residual "
             f"{r['total_residual_mean_second_half']:.4e} m/s, overlap {r['overlap_bodies_mean']:.0f}, "
             f"{r['ms_per_step']:.2f} ms/step")
-    head = next(r for r in runs if r["k"] == sc.halo_k and r["weights"] == "geodesic")
+    head = next(r for r in runs if r["k"] == sc.halo_k and r["weights"] == "geodesic" and r["coupling"] == "none")
     out = {
         "metric": "summed ball-joint violation |C| of the blended state, mean over steps 250-500 (lower is better)",
         "value": head["joint_violation_sum_mean_second_half"], "unit": "m", "n_gpus": 1, "steps": steps,
@@ -357,7 +363,7 @@ def bench_accuracy(args):
             "workload": (f"chains: 256 chains of 200 ball-jointed spheres r 0.1 m, m 0.5 kg, over 16 static "
                          f"spheres, 16 x-slab partitions, h 1/120 s, 40 sweeps (fixed), beta 4, {steps} steps; "
                          f"exact diagnostics every {every} steps"),
-            "reported": f"k = {sc.halo_k}, geodesic weights",
+            "reported": f"k = {sc.halo_k}, geodesic weights, no interface coupling",
             "runs": runs,
         },
         "roofline": None,
@@ -367,16 +373,15 @@ def bench_accuracy(args):
 
 
 def cpu_baseline_lb(sc, tol, cap, n_steps=130):
-    """The oracle on the first n_steps steps of the same run (carried sets and keys)."""
+    """The oracle on the first n_steps steps of the same run (carried sets and warm-start cache)."""
     import oracle
 
-    st, m, prev, o = sc.state, oracle.initial_masks(sc), np.zeros(0, np.uint64), None
+    st, m, o = sc.state, oracle.initial_masks(sc), None
     t0 = time.perf_counter()
     sweeps = 0
     for _ in range(n_steps):
-        o = oracle.step(sc, state=st, cache=o, lb_masks=m, lb_prev_keys=prev, lb_depth=0, adaptive=True, tol=tol,
-                        max_iters=cap)
-        st, m, prev = o["state"].astype(np.float32), o["mask"].astype(np.uint64), o["contact_key"].astype(np.uint64)
+        o = oracle.step(sc, state=st, cache=o, lb_masks=m, lb_depth=0, adaptive=True, tol=tol, max_iters=cap)
+        st, m = o["state"].astype(np.float32), o["mask"].astype(np.uint64)
         sweeps += int(o["max_iters"])
     dt = time.perf_counter() - t0
     return {"value": sc.n_bodies * n_steps / dt, "unit": "body-steps/s", "cores": 1, "kind": "oracle",
