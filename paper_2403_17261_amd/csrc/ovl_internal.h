@@ -180,6 +180,8 @@ struct WP {
   int32_t* wc_kind;             // [Mcap]
   uint64_t* wc_key;             // [Mcap]
   float* wc_val;                // [4][Mcap]
+  uint64_t* wc_k64;             // [Mcap] search key of each entry: kind << 63 | key
+  int32_t* wc_off;              // [G+1] entries of partition p: [wc_off[p], wc_off[p+1])
   // Gauss-Seidel schedule
   int32_t* part_order;          // [G] partitions by descending copy count
   int32_t* pgs_queue;           // [2] work counters of the persistent kernels (LDS, global)

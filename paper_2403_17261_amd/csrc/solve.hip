@@ -393,19 +393,21 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
 
 // ----------------------------------------------------------------- rows ----
 
+// Warm-start cache lookup: the previous step's entries of partition `part`
+// are [wc_off[part], wc_off[part+1]), sorted by kind << 63 | key.  n: the
+// number of entries (0: no cache).
 __device__ __forceinline__ int cache_find(const WP& w, int n, int part, int kind, uint64_t key) {
-  int lo = 0, hi = n;
+  if (n <= 0) return -1;
+  const uint64_t k = ((uint64_t)kind << 63) | key;
+  int lo = w.wc_off[part], hi = w.wc_off[part + 1];
   while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    int pm = w.wc_part[mid], km = w.wc_kind[mid];
-    uint64_t xm = w.wc_key[mid];
-    bool less = pm < part || (pm == part && (km < kind || (km == kind && xm < key)));
-    if (less)
+    const int mid = (lo + hi) >> 1;
+    if (w.wc_k64[mid] < k)
       lo = mid + 1;
     else
       hi = mid;
   }
-  if (lo < n && w.wc_part[lo] == part && w.wc_kind[lo] == kind && w.wc_key[lo] == key) return lo;
+  if (lo < w.wc_off[part + 1] && w.wc_k64[lo] == k) return lo;
   return -1;
 }
 
@@ -1350,6 +1352,7 @@ __global__ void k_cache(WP w) {
   if (src < w.J) {
     w.wc_kind[u] = 0;
     w.wc_key[u] = (uint64_t)src;
+    w.wc_k64[u] = (uint64_t)src;
     w.wc_val[u] = l.x;
     w.wc_val[MC + u] = l.y;
     w.wc_val[2 * MC + u] = l.z;
@@ -1358,6 +1361,7 @@ __global__ void k_cache(WP w) {
     const int c = src - w.J;
     w.wc_kind[u] = 1;
     w.wc_key[u] = ((uint64_t)w.c_a[c] << 32) | w.c_bkey[c];
+    w.wc_k64[u] = (1ull << 63) | w.wc_key[u];
     const float4 r0 = w.r_rec[slot];
     f3 t1, t2;
     tangents_from(mk(r0.x, r0.y, r0.z), r0.w, t1, t2);
@@ -1379,6 +1383,8 @@ __global__ __launch_bounds__(kCommitBS) void k_commit(WP w) {
   if (threadIdx.x == 0) failed_s = w.scal[SC_FLAGS] != 0;
   __syncthreads();
   if (failed_s) return;
+  // the cache written by k_cache is indexed by this step's partition ranges
+  for (int g = threadIdx.x; g <= w.G; g += kCommitBS) w.wc_off[g] = w.part_copy_off[g];
   int mx = 0;
   long long unconv = 0, bytes = 0, sweeps = 0;
   for (int g = threadIdx.x; g < w.G; g += kCommitBS) {

@@ -170,6 +170,7 @@ struct ovl_world {
     w.wc_kind = alloc<int32_t>(g, Mcap, ok);
     w.wc_key = alloc<uint64_t>(g, Mcap, ok);
     w.wc_val = alloc<float>(g, (size_t)4 * Mcap, ok);
+    w.wc_k64 = alloc<uint64_t>(g, Mcap, ok);
     w.mc_blk[2] = alloc<int32_t>(g, (size_t)(nblocks(Ccap, 256) + 1) * 64, ok);
     return ok;
   }
@@ -218,6 +219,7 @@ struct ovl_world {
     w.part_resid = alloc<float>(g, G_ + 1, ok);
     w.part_rsum = alloc<float>(g, G_ + 1, ok);
     w.part_order = alloc<int32_t>(g, G_ + 1, ok);
+    w.wc_off = alloc<int32_t>(g, G_ + 1, ok);
     return ok;
   }
 
@@ -339,6 +341,7 @@ struct ovl_world {
     d2d(wp.wc_part, old.wc_part, keep * sizeof(int32_t));
     d2d(wp.wc_kind, old.wc_kind, keep * sizeof(int32_t));
     d2d(wp.wc_key, old.wc_key, keep * sizeof(uint64_t));
+    d2d(wp.wc_k64, old.wc_k64, keep * sizeof(uint64_t));
     for (int k = 0; k < 4; ++k) d2d(wp.wc_val + (size_t)k * wp.Mcap, old.wc_val + (size_t)k * old.Mcap, keep * sizeof(float));
     ok = ok && hipStreamSynchronize(stream) == hipSuccess;
     free_group(old_allocs);
@@ -1160,6 +1163,7 @@ ovl_status ovl_write_cache(ovl_world* w, const int32_t* part, const int32_t* kin
       return w->fail(OVL_ERR_INVALID_ARG, "cache entry with a bad partition or kind");
     for (int k = 0; k < 4; ++k)
       if (!std::isfinite(val[4 * i + k])) return w->fail(OVL_ERR_INVALID_ARG, "non-finite cached impulse");
+    if ((key[i] >> 63) != 0) return w->fail(OVL_ERR_INVALID_ARG, "cache key out of range");
     if (i > 0) {
       const bool less = part[i - 1] < part[i] ||
                         (part[i - 1] == part[i] && (kind[i - 1] < kind[i] || (kind[i - 1] == kind[i] && key[i - 1] < key[i])));
@@ -1170,8 +1174,18 @@ ovl_status ovl_write_cache(ovl_world* w, const int32_t* part, const int32_t* kin
   std::vector<float> cols((size_t)4 * MC, 0.0f);
   for (int64_t i = 0; i < n; ++i)
     for (int k = 0; k < 4; ++k) cols[(size_t)k * MC + i] = val[4 * i + k];
+  // the search index: a 64-bit key per entry and each partition's range
+  std::vector<uint64_t> k64((size_t)n);
+  std::vector<int32_t> off((size_t)w->G + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    k64[i] = ((uint64_t)kind[i] << 63) | key[i];
+    off[part[i] + 1]++;
+  }
+  for (int g = 0; g < w->G; ++g) off[g + 1] += off[g];
   if (hipStreamSynchronize(w->stream) != hipSuccess || !w->upload(w->wp.wc_part, part, n * sizeof(int32_t)) ||
       !w->upload(w->wp.wc_kind, kind, n * sizeof(int32_t)) || !w->upload(w->wp.wc_key, key, n * sizeof(uint64_t)) ||
+      !w->upload(w->wp.wc_k64, k64.data(), n * sizeof(uint64_t)) ||
+      !w->upload(w->wp.wc_off, off.data(), off.size() * sizeof(int32_t)) ||
       !w->upload(w->wp.wc_val, cols.data(), cols.size() * sizeof(float)) || hipStreamSynchronize(w->stream) != hipSuccess)
     return w->fail(OVL_ERR_DEVICE, "upload failed");
   w->write_scal(SC_PREV_NCOPY, (int32_t)n);
