@@ -521,6 +521,8 @@ def main():
         t1 = time.perf_counter()
         c1 = w.counters()
         last = w.step(0, stats=True)
+        # untimed: the exact natural-map residual of the step after the timed ones
+        nxt = w.step(1, stats=True, exact=True)
         secs = t1 - t0
         steps_done = c1["steps"] - c0["steps"]
         if steps_done != args.steps:
@@ -530,7 +532,8 @@ def main():
              "pgs_bytes": c1["pgs_bytes"] - c0["pgs_bytes"],
              "sweeps_mean": (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / max(1, steps_done),
              "sweeps_part_mean": (c1["sweeps_part_total"] - c0["sweeps_part_total"]) / max(1, steps_done * w.G),
-             "unconverged": c1["unconverged_total"] - c0["unconverged_total"], "last": last}
+             "unconverged": c1["unconverged_total"] - c0["unconverged_total"], "last": last,
+             "steps_capped": c1["steps_capped"] - c0["steps_capped"], "exact_next": nxt["resid_exact"]}
         r["achieved"] = r["pgs_bytes"] / (r["pgs_ms"] * 1e-3) / 1e9 if r["pgs_ms"] > 0 else 0.0
         runs[mode_name] = r
         log(f"[{mode_name}] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step, solver "
@@ -577,7 +580,9 @@ def main():
             "learned_vs_plain": {k: {"body_steps_per_s": v["value"], "ms_per_step": v["ms_per_step"],
                                      "sweeps_per_step": round(v["sweeps_mean"], 2),
                                      "partition_sweeps_per_step": round(v["sweeps_part_mean"], 2),
-                                     "unconverged_partition_steps": int(v["unconverged"])}
+                                     "unconverged_partition_steps": int(v["unconverged"]),
+                                     "steps_hitting_cap_pct": round(100.0 * v["steps_capped"] / args.steps, 2),
+                                     "exact_residual_step_after": v["exact_next"]}
                                  for k, v in runs.items()},
             "mean_sweeps_per_step": round(sweeps_mean, 2), "unconverged_partition_steps": int(unconv),
             "last_step": {k: last[k] for k in ("n_contacts", "n_copies", "n_replicas", "n_overlap",

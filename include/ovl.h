@@ -349,6 +349,7 @@ typedef struct {
                                  copy 220 B (two bodies), 164 B (one body and a static), 192 B (joint) */
   int64_t pgs_launches;       /* solver launches timed with HIP events (profiling on) */
   double pgs_ms;              /* their summed duration, ms, measured on the world's stream */
+  int64_t steps_capped;       /* steps in which a partition hit the cap unconverged (adaptive mode) */
 } ovl_counters;
 ovl_status ovl_get_counters(ovl_world* w, ovl_counters* out);
 

@@ -1419,6 +1419,7 @@ __global__ __launch_bounds__(kCommitBS) void k_commit(WP w) {
     w.stat_i64[2] += t[2];
     w.stat_i64[3] += t[3];
     w.stat_i64[4] += 1;
+    w.stat_i64[5] += t[1] > 0 ? 1 : 0;
   }
 }
 

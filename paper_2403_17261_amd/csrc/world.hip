@@ -1096,6 +1096,7 @@ ovl_status ovl_get_counters(ovl_world* w, ovl_counters* out) {
   out->pgs_bytes = c[2];
   out->pgs_launches = w->pgs_launches;
   out->pgs_ms = w->pgs_ms;
+  out->steps_capped = c[5];
   return OVL_OK;
 }
 
