@@ -593,6 +593,18 @@ __device__ void write_features(const WP& w, int u, int src, int p, float l0, flo
   f[13] = f[14] = f[15] = 0.0f;
 }
 
+// Ids of a copy in 32 bits: local replica a (bits 0-13), joint (14), capsule
+// rows (15), local replica b + 1 (bits 16-31; 0 = static).  Stored, as bits,
+// in the fourth component of the copy's impulse, which the sweeps load anyway.
+constexpr int kPackReps = 16384;
+
+__device__ __forceinline__ float pack_ids(int2 id) {
+  const uint32_t ia = (uint32_t)(id.x & ~(kJointFlag | kGenFlag));
+  const uint32_t pk = ia | ((id.x & kJointFlag) ? 0x4000u : 0u) | ((id.x & kGenFlag) ? 0x8000u : 0u) |
+                      ((uint32_t)(id.y + 1) << 16);
+  return __uint_as_float(pk);
+}
+
 __global__ void k_rows(WP w) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   const int M = w.part_copy_off[w.G];
@@ -710,8 +722,10 @@ __global__ void k_rows(WP w) {
       }
     }
   }
-  w.r_lam0[slot] = make_float4(l0, l1, l2, 0.0f);
-  w.r_lam[slot] = make_float4(l0, l1, l2, 0.0f);
+  // partitions with fewer than kPackReps replicas carry the ids in the impulse's fourth component
+  const float pk = w.part_rep_off[p + 1] - w.part_rep_off[p] < kPackReps ? pack_ids(w.r_ids[slot]) : 0.0f;
+  w.r_lam0[slot] = make_float4(l0, l1, l2, pk);
+  w.r_lam[slot] = make_float4(l0, l1, l2, pk);
   if (w.feat_on) write_features(w, u, src, p, l0, l1, l2);
 }
 
@@ -736,13 +750,15 @@ struct Rec {
 // Issue the loads of a record without using them, so a prefetch does not wait
 // for its data (decode() reads the ids when the record is solved).  kCaps: the
 // world has capsules; the lever-arm records are then always loaded.
+// packed: the partition has fewer than kPackReps replicas, and the impulse's
+// fourth component carries the ids (pack_ids), so r_ids is not read.
 template <bool kCaps>
-__device__ __forceinline__ void fetch_rec(const WP& w, int slot, Rec& R) {
+__device__ __forceinline__ void fetch_rec(const WP& w, int slot, Rec& R, bool packed) {
   const int64_t MC = w.Mcap;
   R.r0 = w.r_rec[slot];
   R.r1 = w.r_rec[MC + slot];
   R.r2 = w.r_rec[2 * MC + slot];
-  R.id = w.r_ids[slot];
+  if (!packed) R.id = w.r_ids[slot];
   R.lam = w.r_lam[slot];
   if (kCaps) {
     R.g0 = w.r_gen[slot];
@@ -751,7 +767,15 @@ __device__ __forceinline__ void fetch_rec(const WP& w, int slot, Rec& R) {
 }
 
 template <bool kCaps>
-__device__ __forceinline__ void decode(Rec& R) {
+__device__ __forceinline__ void decode(Rec& R, bool packed) {
+  if (packed) {
+    const uint32_t pk = __float_as_uint(R.lam.w);
+    R.ia = (int)(pk & 0x3fffu);
+    R.joint = (pk & 0x4000u) != 0;
+    R.gen = kCaps && (pk & 0x8000u) != 0;
+    R.ib = (int)(pk >> 16) - 1;
+    return;
+  }
   R.joint = (R.id.x & kJointFlag) != 0;
   R.gen = kCaps && (R.id.x & kGenFlag) != 0;
   R.ia = R.id.x & ~(kJointFlag | kGenFlag);
@@ -759,9 +783,9 @@ __device__ __forceinline__ void decode(Rec& R) {
 }
 
 template <bool kCaps>
-__device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R) {
-  fetch_rec<kCaps>(w, slot, R);
-  decode<kCaps>(R);
+__device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R, bool packed = false) {
+  fetch_rec<kCaps>(w, slot, R, packed);
+  decode<kCaps>(R, packed);
 }
 
 struct Bod {
@@ -950,7 +974,6 @@ __device__ __forceinline__ void gen_contact_rows(const Rec& R, Bod& A, Bod& B, f
 
 template <bool solve, bool kCaps = false>
 __device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, int slot, int r0 = 0) {
-  decode<kCaps>(R);
   Bod A = ld_body(V, R.ia);
   Bod B;
   const bool hasB = R.ib >= 0;
@@ -1057,12 +1080,13 @@ template <int BS, bool kCaps>
 __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int* coff, int r0, int nr,
                                 bool learned, float* red) {
   const int tid = threadIdx.x;
+  const bool packed = nr < kPackReps;
   float unused = 0.0f;
   for (int c = 0; c < ncol; ++c) {
     const int e = s0 + coff[c + 1];
     for (int slot = s0 + coff[c] + tid; slot < e; slot += BS) {
       Rec R;
-      load_rec<kCaps>(w, slot, R);
+      load_rec<kCaps>(w, slot, R, packed);
       if (learned && !R.joint) R.lam = w.r_lamL[slot];
       if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, unused, slot, r0);
     }
@@ -1071,7 +1095,7 @@ __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int*
   float e = 0.0f;
   for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += BS) {
     Rec R;
-    load_rec<kCaps>(w, slot, R);
+    load_rec<kCaps>(w, slot, R, packed);
     if (learned && !R.joint) R.lam = w.r_lamL[slot];
     const Bod A = ld_body(V, R.ia);
     Bod B = {mk(0, 0, 0), mk(0, 0, 0), 0.0f, 0.0f};
@@ -1094,6 +1118,7 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   const int nr = w.part_rep_off[p + 1] - r0;
   const int s0 = w.part_copy_off[p];
   const int ncol = w.part_ncol[p];
+  const bool packed = nr < kPackReps;  // uniform: ids from the impulses' fourth component
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
   load_replicas<BS>(w, V, r0, nr);
   __syncthreads();
@@ -1106,7 +1131,10 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
     if (w.force_guard && w.part_force_guard[p] >= 0) use = w.part_force_guard[p] != 0;
     if (use)
       for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += BS)
-        if (!(w.r_ids[slot].x & kJointFlag)) w.r_lam[slot] = w.r_lamL[slot];
+        if (!(w.r_ids[slot].x & kJointFlag)) {
+          const float4 L = w.r_lamL[slot];
+          w.r_lam[slot] = make_float4(L.x, L.y, L.z, w.r_lam[slot].w);
+        }
     if (tid == 0) {
       w.part_guard[p] = use ? 1 : 0;
       w.part_rho0[2 * p] = rho_p;
@@ -1119,7 +1147,7 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
     const int e = s0 + coff[c + 1];
     for (int slot = s0 + coff[c] + tid; slot < e; slot += BS) {
       Rec R;
-      load_rec<kCaps>(w, slot, R);
+      load_rec<kCaps>(w, slot, R, packed);
       if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, rl, slot, r0);
     }
     __syncthreads();
@@ -1138,7 +1166,7 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   auto co = [&](int k) { return k < 64 ? __builtin_amdgcn_readlane(cv0, k) : cv1; };
   Rec cur;
   bool has_cur = ncol > 1 && co(0) + tid < co(1);
-  if (has_cur) fetch_rec<kCaps>(w, s0 + co(0) + tid, cur);
+  if (has_cur) fetch_rec<kCaps>(w, s0 + co(0) + tid, cur, packed);
   // Nothing may still be in flight into `cur` when the loop is entered:
   // otherwise the wait placed before its first use would also hold back the
   // next colour's prefetch in every iteration.
@@ -1150,12 +1178,15 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
       const int b0 = co(c), b1 = co(c + 1), n0 = co(cn), n1 = co(cn + 1);
       Rec nxt;
       const bool has_nxt = ncol > 1 && n0 + tid < n1;
-      if (has_nxt) fetch_rec<kCaps>(w, s0 + n0 + tid, nxt);
-      if (has_cur) do_slot<true, kCaps>(w, V, cur, rl, s0 + b0 + tid, r0);
+      if (has_nxt) fetch_rec<kCaps>(w, s0 + n0 + tid, nxt, packed);
+      if (has_cur) {
+        decode<kCaps>(cur, packed);
+        do_slot<true, kCaps>(w, V, cur, rl, s0 + b0 + tid, r0);
+      }
       const int e = s0 + b1;
       for (int slot = s0 + b0 + tid + first; slot < e; slot += BS) {
         Rec R;
-        load_rec<kCaps>(w, slot, R);
+        load_rec<kCaps>(w, slot, R, packed);
         do_slot<true, kCaps>(w, V, R, rl, slot, r0);
       }
       __syncthreads();
