@@ -188,6 +188,7 @@ struct WP {
   int32_t pgs_cfg;              // index into kPgsCfg*
   int32_t pgs_persistent;       // 1: resident workgroups take partitions from the queue
   int32_t pgs_grid[2];          // resident workgroups of the two persistent kernels
+  int32_t n_cu;                 // compute units of the device
   // per-partition results
   int32_t* part_iters;          // [G]
   int32_t* part_nstatic;        // [G] contact copies with a static body

@@ -114,23 +114,38 @@ __device__ __forceinline__ bool prio_gt(uint32_t ha, int ua, uint32_t hb, int ub
 // ------------------------------------------------------------ colouring ----
 
 constexpr int kColBS = 1024;
-constexpr int kColWaves = kColBS / 64;
 constexpr int kColLds = 16384;  // partitions with at most this many copies colour in LDS (7 B per copy)
 constexpr int kColRepLds = 8192;  // ... and at most this many replicas (incidence offsets in LDS)
+// Small partitions colour in a 256-thread workgroup with 39 KB of LDS, four to
+// a compute unit, when there are more partitions than compute units (many
+// scenes at once).  At most 16 copies per thread.
+constexpr int kColSmallBS = 256;
+constexpr int kColSmallCopies = 4096;
+constexpr int kColSmallReps = 4096;
 
-__global__ __launch_bounds__(kColBS) void k_colour(WP w) {
-  __shared__ int lds_i[kColWaves];
+// BS threads; partitions of at most kCopies copies and kReps replicas colour
+// in LDS.  kSmall: this instantiation takes only the partitions that fit the
+// small one (kColSmallCopies, kColSmallReps); the large one takes the rest
+// when split is set, else every partition.
+template <int BS, int kCopies, int kReps, bool kSmall>
+__global__ __launch_bounds__(BS) void k_colour(WP w, int split) {
+  __shared__ int lds_i[(BS / 64)];
   __shared__ int ccount[kMaxColours];
   __shared__ int col_off[kColStride];
   __shared__ int running[kMaxColours];
-  __shared__ int wcnt[kColWaves][kMaxColours];
+  __shared__ int wcnt[(BS / 64)][kMaxColours];
   __shared__ int any_s;
-  __shared__ signed char col_lds[kColLds];
-  __shared__ uint32_t wait_lds[kColLds / 2];  // two 16-bit counters per word
-  __shared__ uint16_t inc_l[2 * kColLds];     // incidence lists: local copy indices
-  __shared__ uint16_t ioff_l[kColRepLds + 1];  // per local replica, into inc_l
+  __shared__ signed char col_lds[kCopies];
+  __shared__ uint32_t wait_lds[kCopies / 2];  // two 16-bit counters per word
+  __shared__ uint16_t inc_l[2 * kCopies];     // incidence lists: local copy indices
+  __shared__ uint16_t ioff_l[kReps + 1];  // per local replica, into inc_l
   const int p = w.part_order[blockIdx.x];  // largest partitions first
   const int tid = threadIdx.x;
+  {
+    const int nc = w.part_copy_off[p + 1] - w.part_copy_off[p], nrp = w.part_rep_off[p + 1] - w.part_rep_off[p];
+    const bool small = nc <= kColSmallCopies && nrp <= kColSmallReps;
+    if (kSmall ? !small : (split && small)) return;  // uniform
+  }
   if (tid == 0) any_s = (w.scal[SC_FLAGS] & (F_CONTACT_CAP | F_ADJ_CAP | F_REP_CAP | F_COPY_CAP)) ? 1 : 0;
   __syncthreads();
   if (any_s) return;
@@ -144,18 +159,18 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   // also go to global memory (the conflict-degree feature reads them).
   // The LDS path keeps 16-bit wait counters: every replica must touch fewer
   // than 2^14 copies so that a copy's count stays below 2^15.  Uniform.
-  bool in_lds = u1 - u0 <= kColLds && nr <= kColRepLds;
+  bool in_lds = u1 - u0 <= kCopies && nr <= kReps;
   if (in_lds) {
-    for (int i = tid; i < (nr + 1) / 2; i += kColBS) wait_lds[i] = 0u;
+    for (int i = tid; i < (nr + 1) / 2; i += BS) wait_lds[i] = 0u;
     __syncthreads();
-    for (int u = u0 + tid; u < u1; u += kColBS) {
+    for (int u = u0 + tid; u < u1; u += BS) {
       const int ia = w.cp_ia[u], ib = w.cp_ib[u];
       atomicAdd(&wait_lds[ia >> 1], 1u << (16 * (ia & 1)));
       if (ib >= 0) atomicAdd(&wait_lds[ib >> 1], 1u << (16 * (ib & 1)));
     }
     __syncthreads();
     bool busy = false;
-    for (int r = tid; r < nr; r += kColBS) {
+    for (int r = tid; r < nr; r += BS) {
       const int c = (wait_lds[r >> 1] >> (16 * (r & 1))) & 0xffff;
       busy |= c >= (1 << 14);
       inc_cnt[r0 + r] = c;
@@ -164,19 +179,19 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   }
   if (in_lds) {
     int carry = 0;
-    for (int base = 0; base < nr; base += kColBS) {
+    for (int base = 0; base < nr; base += BS) {
       const int r = base + tid;
       const int v = r < nr ? (wait_lds[r >> 1] >> (16 * (r & 1))) & 0xffff : 0;
       int tot;
-      const int pre = block_excl_scan<kColBS>(v, lds_i, tot);
+      const int pre = block_excl_scan<BS>(v, lds_i, tot);
       if (r < nr) ioff_l[r] = (uint16_t)(carry + pre);
       carry += tot;
     }
     if (tid == 0) ioff_l[nr] = (uint16_t)carry;
     __syncthreads();
-    for (int i = tid; i < (nr + 1) / 2; i += kColBS) wait_lds[i] = 0u;
+    for (int i = tid; i < (nr + 1) / 2; i += BS) wait_lds[i] = 0u;
     __syncthreads();
-    for (int u = u0 + tid; u < u1; u += kColBS) {
+    for (int u = u0 + tid; u < u1; u += BS) {
       const int ia = w.cp_ia[u], ib = w.cp_ib[u];
       const int ka = (atomicAdd(&wait_lds[ia >> 1], 1u << (16 * (ia & 1))) >> (16 * (ia & 1))) & 0xffff;
       inc_l[ioff_l[ia] + ka] = (uint16_t)(u - u0);
@@ -186,26 +201,26 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
       }
     }
     __syncthreads();
-    for (int u = u0 + tid; u < u1; u += kColBS) col_lds[u - u0] = -1;
-    for (int i = tid; i < (u1 - u0 + 1) / 2; i += kColBS) wait_lds[i] = 0u;
+    for (int u = u0 + tid; u < u1; u += BS) col_lds[u - u0] = -1;
+    for (int i = tid; i < (u1 - u0 + 1) / 2; i += BS) wait_lds[i] = 0u;
     __syncthreads();
   } else {
-    for (int r = tid; r < nr; r += kColBS) inc_cnt[r0 + r] = 0;
+    for (int r = tid; r < nr; r += BS) inc_cnt[r0 + r] = 0;
     __syncthreads();
-    for (int u = u0 + tid; u < u1; u += kColBS) {
+    for (int u = u0 + tid; u < u1; u += BS) {
       atomicAdd(&inc_cnt[r0 + w.cp_ia[u]], 1);
       int ib = w.cp_ib[u];
       if (ib >= 0) atomicAdd(&inc_cnt[r0 + ib], 1);
     }
     __syncthreads();
-    for (int u = u0 + tid; u < u1; u += kColBS) w.cp_colour[u] = -1;
+    for (int u = u0 + tid; u < u1; u += BS) w.cp_colour[u] = -1;
     {
       int carry = 2 * u0;
-      for (int base = 0; base < nr; base += kColBS) {
+      for (int base = 0; base < nr; base += BS) {
         int r = base + tid;
         int v = r < nr ? inc_cnt[r0 + r] : 0;
         int tot;
-        int pre = block_excl_scan<kColBS>(v, lds_i, tot);
+        int pre = block_excl_scan<BS>(v, lds_i, tot);
         if (r < nr) {
           w.inc_off[r0 + r] = carry + pre;
           inc_cnt[r0 + r] = 0;
@@ -214,7 +229,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
       }
     }
     __syncthreads();
-    for (int u = u0 + tid; u < u1; u += kColBS) {
+    for (int u = u0 + tid; u < u1; u += BS) {
       int ia = r0 + w.cp_ia[u];
       w.inc[w.inc_off[ia] + atomicAdd(&inc_cnt[ia], 1)] = u;
       int ib = w.cp_ib[u];
@@ -238,10 +253,10 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
     return __ffsll((unsigned long long)~used) - 1;
   };
   if (in_lds) {
-    const int per = (u1 - u0 + kColBS - 1) / kColBS;  // copies per thread, at most 16
+    const int per = (u1 - u0 + BS - 1) / BS;  // copies per thread, at most 16
     uint32_t todo = 0;
     for (int j = 0; j < per; ++j) {
-      const int u = u0 + tid + j * kColBS;
+      const int u = u0 + tid + j * BS;
       if (u >= u1) break;
       todo |= 1u << j;
       const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
@@ -268,7 +283,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
       uint32_t now = 0;
       for (uint32_t t = todo; t; t &= t - 1) {
         const int j = __ffs(t) - 1;
-        const int u = u0 + tid + j * kColBS;
+        const int u = u0 + tid + j * BS;
         const uint32_t wv = wait_lds[(u - u0) >> 1] >> (16 * ((u - u0) & 1));
         if ((wv & 0xffffu) != 0) continue;
         uint64_t used = 0;
@@ -288,7 +303,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
       __syncthreads();
       for (uint32_t t = now; t; t &= t - 1) {
         const int j = __ffs(t) - 1;
-        const int u = u0 + tid + j * kColBS;
+        const int u = u0 + tid + j * BS;
         const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
         const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
         for (int e = 0; e < 2; ++e) {
@@ -306,7 +321,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   } else {
     for (;;) {
       bool pending = false;
-      for (int u = u0 + tid; u < u1; u += kColBS) {
+      for (int u = u0 + tid; u < u1; u += BS) {
         if (__hip_atomic_load(&w.cp_colour[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= 0) continue;
         const uint32_t hu = fmix32((uint32_t)u ^ w.seed);
         uint64_t used = 0;
@@ -337,7 +352,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   }
   if (__syncthreads_or(overflow) && tid == 0) atomicOr(&w.scal[SC_FLAGS], F_COLOUR_CAP);
   if (in_lds)  // a copy left uncoloured by the round bound gets a valid colour (the step is flagged)
-    for (int u = u0 + tid; u < u1; u += kColBS) w.cp_colour[u] = col_lds[u - u0] < 0 ? kMaxColours - 1 : col_lds[u - u0];
+    for (int u = u0 + tid; u < u1; u += BS) w.cp_colour[u] = col_lds[u - u0] < 0 ? kMaxColours - 1 : col_lds[u - u0];
   __syncthreads();
   // colour histogram and offsets
   if (tid < kMaxColours) {
@@ -345,7 +360,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
     running[tid] = 0;
   }
   __syncthreads();
-  for (int u = u0 + tid; u < u1; u += kColBS) atomicAdd(&ccount[w.cp_colour[u]], 1);
+  for (int u = u0 + tid; u < u1; u += BS) atomicAdd(&ccount[w.cp_colour[u]], 1);
   __syncthreads();
   if (tid == 0) {
     int acc = 0, ncol = 0;
@@ -361,7 +376,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
   if (tid < kColStride) w.part_col_off[p * kColStride + tid] = col_off[tid];
   // stable slots: rank inside the colour in uid order
   const int wave = tid >> 6;
-  for (int base = u0; base < u1; base += kColBS) {
+  for (int base = u0; base < u1; base += BS) {
     const int u = base + tid;
     const int col = u < u1 ? w.cp_colour[u] : -1;
     wcnt[wave][lane_id()] = 0;
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(kColBS) void k_colour(WP w) {
     __syncthreads();
     if (tid < kMaxColours) {
       int t = 0;
-      for (int q = 0; q < kColWaves; ++q) t += wcnt[q][tid];
+      for (int q = 0; q < (BS / 64); ++q) t += wcnt[q][tid];
       running[tid] += t;
     }
     __syncthreads();
@@ -1736,7 +1751,11 @@ hipError_t launch_solve_pre(const WP& w, hipStream_t s) {
   if (w.G > 0) {
     k_part_order<<<nblocks(w.G, kOrderBS), kOrderBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
-    k_colour<<<w.G, kColBS, 0, s>>>(w);
+    // with more partitions than compute units the small ones colour several
+    // to a compute unit; otherwise every partition has a compute unit of its own
+    const int split = w.G > w.n_cu ? 1 : 0;
+    k_colour<kColBS, kColLds, kColRepLds, false><<<w.G, kColBS, 0, s>>>(w, split);
+    if (split) k_colour<kColSmallBS, kColSmallCopies, kColSmallReps, true><<<w.G, kColSmallBS, 0, s>>>(w, split);
     k_slot_spread<<<w.G, kSpreadBS, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }

@@ -678,8 +678,10 @@ ovl_status ovl_create_world(const ovl_world_desc* d, const ovl_params* params, c
   {
     int dev = 0;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
       w->n_cu = prop.multiProcessorCount;
+      w->wp.n_cu = prop.multiProcessorCount;
+    }
     if (!w->apply_launch(w->launch, 0)) {
       delete w;
       g_create_error = "could not query the occupancy of the solver kernels";

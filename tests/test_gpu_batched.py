@@ -109,3 +109,20 @@ def test_batched_world_through_graph_matches_oracle():
     big = _largest_partition(w)
     log(f"  largest partition {big} replicas (LDS tile 1200)")
     assert st["n_contacts"] > 300 and big > 1200
+
+
+def test_more_partitions_than_compute_units_matches_oracle():
+    """Over one partition per compute unit the small partitions colour in the
+    256-thread variant, several to a compute unit; colours must still equal
+    the oracle's bit for bit."""
+    import torch
+    sc = _batched(n_scenes=110, seed=9, nmax=700)
+    G = int(sc.parts_per_scene.sum())
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    log(f"  {sc.n_bodies} bodies, {G} partitions, {n_cu} compute units")
+    assert G > n_cu
+    w = ovl.World(sc, ovl.make_params(dt=sc.dt, max_iters=sc.iters))
+    w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+    w.step(120)
+    st, o = compare_step(sc, w, w.params, label=f"{G} partitions t=121")
+    assert st["n_contacts"] > 10000

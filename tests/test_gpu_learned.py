@@ -62,14 +62,16 @@ def test_mlp_bf16_inference_matches_oracle():
     assert err.max() < 2e-2
 
 
-@pytest.mark.parametrize("which", ["lattice", "tower"])
-def test_learned_step_matches_oracle(which):
+@pytest.mark.parametrize("which, coupled", [("lattice", False), ("tower", False), ("lattice", True), ("tower", True)])
+def test_learned_step_matches_oracle(which, coupled):
+    """With interface coupling on, the features see the coupled free velocity."""
     if which == "lattice":
         sc = scenes.config1(3)
     else:
         sc = scenes.config5(2, nx=10, ny=10, nz=6, cols=2)
     P = scenes.mlp_initial_weights(11) * np.float32(0.3)
-    p = ovl.make_params(dt=sc.dt, max_iters=sc.iters)
+    p = ovl.make_params(dt=sc.dt, max_iters=sc.iters,
+                        coupling=ovl.COUPLING_PREV_IMPULSE if coupled else ovl.COUPLING_NONE)
     w = ovl.World(sc, p)
     w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
     w.step(3)
@@ -88,7 +90,9 @@ def test_learned_step_matches_oracle(which):
     fe = np.abs(feat[kinds == 1] - o["copy_feat"][kinds == 1]).max()
     sc_ = np.maximum(1.0, np.abs(o["copy_lambdal"]).max())
     le = np.abs(laml - o["copy_lambdal"]).max() / sc_
-    log(f"  {which}: features max err {fe:.2e}, learned start max rel err {le:.2e}, guard gpu {guard} "
+    if coupled:
+        assert np.abs(o["rep_cpl"]).max() > 0.0
+    log(f"  {which}{' coupled' if coupled else ''}: features max err {fe:.2e}, learned start max rel err {le:.2e}, guard gpu {guard} "
         f"oracle {o['part_guard']}, rho0 gpu {rho0.tolist()} oracle {o['part_rho0'].tolist()}")
     assert fe < 1e-4
     assert le < 2e-2
