@@ -1,9 +1,11 @@
 """Helpers for the GPU-vs-oracle parity tests (no method arithmetic here).
 
-compare_step() advances a GPU world by one step from its current state and
-runs the oracle from the very same float32 state and warm-start cache, then
-compares every intermediate result: integer structures bit for bit, floating
-point within the tolerances stated below.
+compare_step() writes a start into a GPU world -- the scene's synthetic
+initial state, or a state and warm-start cache the oracle produced
+(oracle_run) -- advances the world by one step, runs the oracle from the same
+start, and compares every intermediate result: integer structures bit for
+bit, floating point within the tolerances stated below.  No oracle input is
+read back from the GPU library.
 
 Tolerances (FP32 GPU path against the FP64 oracle after one step):
   velocity   |v - v_ref| <= 1e-4 * max(|v_ref|, g h)          per body
@@ -57,18 +59,57 @@ def check_state(sc, gpu, ref, dt, label=""):
     assert worst["q"] <= 1e-5, f"{label}: quaternion error {worst['q']}"
 
 
-def compare_step(sc, w, params, owner=None, pps=None, halo_k=None, beta=None, forced=None, label="",
-                 check_lambda0=True, lb=None):
-    """One GPU step from the world's current state against one oracle step from the same inputs.
+def oracle_run(sc, params, steps, state=None, cache=None, owner=None, pps=None, halo_k=None, beta=None, lb=None,
+               **extra):
+    """`steps` oracle steps from `state` (default: the scene's initial state)
+    and `cache`, each fed its own output.  Returns (state as float32, the last
+    output: its warm-start cache, and with lb its worker sets in "mask").
+    lb: dict(sets=, depth=) carries the worker sets of dynamic load balancing."""
+    halo_k = sc.halo_k if halo_k is None else halo_k
+    beta = sc.beta if beta is None else beta
+    kw = oracle_kwargs(sc, params, halo_k, beta)
+    kw.update(extra)
+    st = (sc.state if state is None else state).astype(np.float32)
+    out = cache
+    sets = None if lb is None else np.asarray(lb["sets"], np.uint64)
+    for _ in range(steps):
+        if lb is not None:
+            kw.update(lb_masks=sets, lb_depth=int(lb["depth"]))
+        out = oracle.step(sc, state=st, owner=owner, parts_per_scene=pps, cache=out, **kw)
+        st = out["state"].astype(np.float32)
+        if lb is not None:
+            sets = out["mask"].astype(np.uint64)
+    return st, out
 
+
+def next_start(o):
+    """The start of the step after an oracle step: its state and cache."""
+    return o["state"].astype(np.float32), o
+
+
+def compare_step(sc, w, params, start=None, owner=None, pps=None, halo_k=None, beta=None, forced=None, label="",
+                 check_lambda0=True, lb=None):
+    """One GPU step against one oracle step from the same start.
+
+    start: None (the scene's initial state, no warm-start cache) or
+    (state, cache) from the oracle; it is written into the world first.
     lb: None (k-hop halo sets), or dict(sets=, depth=) giving the carried worker
-    sets the world holds for this step and the growth depth."""
+    sets for this step and the growth depth; they are written into the world
+    too, unless lb["carried"] says the world holds them from its last step
+    (which the previous comparison found equal to the oracle's)."""
     halo_k = sc.halo_k if halo_k is None else halo_k
     beta = sc.beta if beta is None else beta
     owner = sc.owner if owner is None else owner
     pps = sc.parts_per_scene if pps is None else pps
-    s0 = w.read_state()
-    cache = w.cache() if params.warmstart or params.coupling else None
+    s0, cache = (sc.state.astype(np.float32), None) if start is None else start
+    s0 = np.ascontiguousarray(s0, np.float32)
+    w.write_state(s0, keep_cache=False)
+    if cache is not None and len(cache["cache_part"]):
+        w.write_cache(cache)
+    else:
+        cache = None
+    if lb is not None and not lb.get("carried", False):
+        w.set_load_balance(True, int(lb["depth"]), sets=np.asarray(lb["sets"], np.uint64))
     if forced is not None:
         w.force_iters(forced)
     stats = w.step(1, stats=True)

@@ -19,7 +19,7 @@ import pytest
 import oracle
 import paper_2403_17261_amd as ovl
 from paper_2403_17261_amd import scenes
-from parity import compare_step, log, oracle_kwargs
+from parity import compare_step, log, next_start, oracle_kwargs, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -38,8 +38,8 @@ def test_equal_weights_parity():
     nw = np.bitwise_count(o["mask"].astype(np.uint64))[o["rep_body"]]
     assert np.array_equal(o["rep_w"], 1.0 / nw)
     assert (nw > 1).sum() > 100
-    w.step(60)
-    compare_step(sc, w, p, label="chains, equal weights t=61")
+    s, c = next_start(o)
+    compare_step(sc, w, p, start=oracle_run(sc, p, 60, state=s, cache=c), label="chains, equal weights t=61")
 
 
 @pytest.mark.parametrize("weights", [ovl.WEIGHTS_GEODESIC, ovl.WEIGHTS_EQUAL])

@@ -11,7 +11,7 @@ import pytest
 
 import paper_2403_17261_amd as ovl
 from paper_2403_17261_amd import scenes
-from parity import compare_step, log
+from parity import compare_step, log, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -104,8 +104,8 @@ def test_batched_world_through_graph_matches_oracle():
     w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
     w.set_launch(pgs_block=256, pgs_lds_reps=1200, persistent=1, graph=1)
     p = w.params
-    w.step(150)
-    st, o = compare_step(sc, w, p, label="batched t=151 (graph, persistent)")
+    w.step(2)                       # the graph is captured and replayed before the compared step
+    st, o = compare_step(sc, w, p, start=oracle_run(sc, p, 150), label="batched t=151 (graph, persistent)")
     big = _largest_partition(w)
     log(f"  largest partition {big} replicas (LDS tile 1200)")
     assert st["n_contacts"] > 300 and big > 1200
@@ -123,6 +123,11 @@ def test_more_partitions_than_compute_units_matches_oracle():
     assert G > n_cu
     w = ovl.World(sc, ovl.make_params(dt=sc.dt, max_iters=sc.iters))
     w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
-    w.step(120)
-    st, o = compare_step(sc, w, w.params, label=f"{G} partitions t=121")
+    # every scene's pile squeezed to 30% of its height, so contacts come at once
+    st0 = sc.state.copy()
+    for s in range(sc.n_scenes):
+        m = sc.scene == s
+        z0 = st0[m, 2].min()
+        st0[m, 2] = (z0 + (st0[m, 2] - z0) * 0.3).astype(np.float32)
+    st, o = compare_step(sc, w, w.params, start=oracle_run(sc, w.params, 3, state=st0), label=f"{G} partitions t=4")
     assert st["n_contacts"] > 10000

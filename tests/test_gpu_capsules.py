@@ -12,7 +12,7 @@ import pytest
 import oracle
 import paper_2403_17261_amd as ovl
 from paper_2403_17261_amd import scenes
-from parity import check_state, compare_step, log, oracle_kwargs
+from parity import check_state, compare_step, log, next_start, oracle_kwargs, oracle_run
 
 pytestmark = pytest.mark.gpu
 G = 9.81
@@ -66,9 +66,8 @@ def _squeezed_pile(n, seed, parts, factor=0.4):
 def test_capsule_pile_first_step():
     sc, st = _squeezed_pile(1500, 4, 4)
     w, p = _world(sc)
-    w.write_state(st, keep_cache=False)
-    s0 = w.read_state()
-    stats, o = compare_step(sc, w, p, label="capsule pile squeezed")
+    s0 = st
+    stats, o = compare_step(sc, w, p, start=(st, None), label="capsule pile squeezed")
     keys = o["contact_key"].astype(np.int64)
     caps = sc.shape == 1
     a, b = keys >> 32, (keys >> 1) & 0x7FFFFFFF
@@ -82,9 +81,9 @@ def test_capsule_pile_first_step():
 def test_capsule_pile_trajectory():
     sc = scenes.capsule_pile(2000, 5, 4, scale=(2000 / 20000.0) ** (1 / 3))
     w, p = _world(sc)
-    compare_step(sc, w, p, label="capsule pile t=0")
-    w.step(150)
-    st, o = compare_step(sc, w, p, label="capsule pile t=151")
+    _, o = compare_step(sc, w, p, label="capsule pile t=0")
+    s, c = next_start(o)
+    st, o = compare_step(sc, w, p, start=oracle_run(sc, p, 150, state=s, cache=c), label="capsule pile t=151")
     plane_caps = sum(1 for k in o["contact_key"].astype(np.int64)
                      if sc.n_bodies <= ((k >> 1) & 0x7FFFFFFF) < sc.n_bodies + sc.planes.shape[0] and
                      sc.shape[k >> 32] == 1)
@@ -117,8 +116,8 @@ def test_capsule_chain_with_joints():
                                joint_anchor=[[0, 0, hl + r, 0, 0, -(hl + r)] for _ in range(n - 1)],
                                owner=owner, n_parts=3, halo_k=2, beta=4, dt=1 / 120.0, iters=40)
     w, p = _world(sc)
-    compare_step(sc, w, p, label="capsule chain t=0")
-    w.step(80)
-    st, o = compare_step(sc, w, p, label="capsule chain t=81")
+    _, o = compare_step(sc, w, p, label="capsule chain t=0")
+    s, c = next_start(o)
+    st, o = compare_step(sc, w, p, start=oracle_run(sc, p, 80, state=s, cache=c), label="capsule chain t=81")
     log(f"  joint violation {float(o['joint_violation']):.2e}")
     assert st["n_contacts"] > 0

@@ -17,7 +17,7 @@ import pytest
 import oracle
 import paper_2403_17261_amd as ovl
 from paper_2403_17261_amd import scenes
-from parity import compare_step, log, oracle_kwargs
+from parity import compare_step, log, next_start, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -29,16 +29,6 @@ def _world(sc, halo_k, **pkw):
     return w, p
 
 
-def _oracle_run(sc, p, halo_k, steps, state=None):
-    """`steps` oracle steps with coupling on, each fed its own state and cache."""
-    kw = oracle_kwargs(sc, p, halo_k, sc.beta)
-    st, cache = (sc.state if state is None else state), None
-    for _ in range(steps):
-        o = oracle.step(sc, state=st, cache=cache, **kw)
-        st, cache = o["state"].astype(np.float32), o
-    return st, cache
-
-
 def _displaced(sc, seed):
     rng = np.random.default_rng(seed)
     st = sc.state.copy()
@@ -46,18 +36,13 @@ def _displaced(sc, seed):
     return st
 
 
-def _start(sc, w, p, halo_k, steps, state=None):
-    st, cache = _oracle_run(sc, p, halo_k, steps, state)
-    w.write_state(st, keep_cache=False)
-    w.write_cache(cache)
-
-
 def test_chains():
     sc = scenes.config3(0, n_chains=16, links=50)
     w, p = _world(sc, sc.halo_k)
-    _start(sc, w, p, sc.halo_k, 2, state=_displaced(sc, 7))
+    start = oracle_run(sc, p, 2, state=_displaced(sc, 7))
     for t in range(2):
-        _, o = compare_step(sc, w, p, label=f"chains coupled step {t + 3}")
+        _, o = compare_step(sc, w, p, start=start, label=f"chains coupled step {t + 3}")
+        start = next_start(o)
     assert (np.abs(o["rep_cpl"]).max(axis=1) > 0).sum() > 20 and np.abs(o["rep_cpl"]).max() > 1e-2
 
 
@@ -67,9 +52,10 @@ def test_lattice_contacts(halo_k):
                                owner_fn=lambda x: scenes.kmeans_owner(x, 6, seed=1)[0])
     sc = scenes._assemble([blk], "lattice-384", halo_k=halo_k, beta=4, dt=1 / 60, iters=30)
     w, p = _world(sc, halo_k)
-    _start(sc, w, p, halo_k, 2)
+    start = oracle_run(sc, p, 2)
     for t in range(2):
-        _, o = compare_step(sc, w, p, label=f"lattice k={halo_k} coupled step {t + 3}")
+        _, o = compare_step(sc, w, p, start=start, label=f"lattice k={halo_k} coupled step {t + 3}")
+        start = next_start(o)
     assert (np.abs(o["rep_cpl"]).max(axis=1) > 0).sum() > 20
 
 
@@ -82,8 +68,8 @@ def test_capsule_pile():
     st[:, 2] += np.float32(0.6)
     st[:, :3] += rng.normal(0, 0.05, st[:, :3].shape).astype(np.float32)
     w, p = _world(sc, 1)
-    _start(sc, w, p, 1, 1, state=st)
-    _, o = compare_step(sc, w, p, halo_k=1, label="capsule pile coupled")
+    start = oracle_run(sc, p, 1, state=st, halo_k=1)
+    _, o = compare_step(sc, w, p, start=start, halo_k=1, label="capsule pile coupled")
     caps = sc.shape[o["rep_body"]] == 1
     assert ((np.abs(o["rep_cpl"]).max(axis=1) > 0) & caps).sum() > 10
 
@@ -93,10 +79,7 @@ def test_with_load_balancing():
     st, out, _ = oracle.run_lb(sc, 4, 0, dt=sc.dt, max_iters=sc.iters, beta=sc.beta)
     sets = out["mask"].astype(np.uint64)
     w, p = _world(sc, 1)
-    w.write_state(st, keep_cache=False)
-    w.write_cache(out)
-    w.set_load_balance(True, 0, sets=sets)
-    _, o = compare_step(sc, w, p, label="bowl, balanced sets, coupled", lb=dict(sets=sets, depth=0))
+    _, o = compare_step(sc, w, p, start=(st, out), label="bowl, balanced sets, coupled", lb=dict(sets=sets, depth=0))
     n = int((np.abs(o["rep_cpl"]).max(axis=1) > 0).sum())
     log(f"  coupled replicas {n}")
     assert n > 20
@@ -106,8 +89,7 @@ def test_several_scenes():
     parts = [scenes.config3(0, n_chains=4, links=40), scenes.config3(1, n_chains=6, links=30)]
     sc = scenes.concat_scenes(parts, halo_k=2, beta=4, dt=1 / 120, iters=40)
     w, p = _world(sc, 2)
-    _start(sc, w, p, 2, 2, state=_displaced(sc, 8))
-    _, o = compare_step(sc, w, p, label="two chain scenes coupled")
+    _, o = compare_step(sc, w, p, start=oracle_run(sc, p, 2, state=_displaced(sc, 8)), label="two chain scenes coupled")
     assert (np.abs(o["rep_cpl"]).max(axis=1) > 0).sum() > 10
 
 

@@ -20,7 +20,7 @@ import pytest
 import oracle
 import paper_2403_17261_amd as ovl
 from paper_2403_17261_amd import scenes
-from parity import compare_step, log
+from parity import compare_step, log, next_start
 
 pytestmark = pytest.mark.gpu
 
@@ -77,7 +77,8 @@ def test_isolated_collision_over_two_steps():
     w.set_load_balance(True, 0)
     _, o1 = compare_step(sc, w, p, label="(i)", lb=dict(sets=[1, 2], depth=0))
     assert o1["mask"].tolist() == [1, 3]
-    _, o2 = compare_step(sc, w, p, label="(iii)", lb=dict(sets=[1, 3], depth=0))
+    _, o2 = compare_step(sc, w, p, start=next_start(o1), label="(iii)",
+                         lb=dict(sets=o1["mask"], depth=0, carried=True))
     assert o2["mask"].tolist() == [1, 1]
 
 
@@ -92,10 +93,7 @@ def test_bowl_from_oracle_state(depth):
     sc = scenes.bowl_naive(1200, 3, 5, squeeze=0.35)
     st, sets, o_prev = _oracle_start(sc, 4, depth)
     w, p = _world(sc)
-    w.write_state(st, keep_cache=False)
-    w.write_cache(o_prev)
-    w.set_load_balance(True, depth, sets=sets)
-    _, o = compare_step(sc, w, p, label=f"bowl 1200 depth {depth}", lb=dict(sets=sets, depth=depth))
+    _, o = compare_step(sc, w, p, start=(st, o_prev), label=f"bowl 1200 depth {depth}", lb=dict(sets=sets, depth=depth))
     changed = int((o["mask"] != sets).sum())
     log(f"  sets changed on {changed} bodies, overlap {o['n_overlap']}")
     assert changed > 0
@@ -118,10 +116,7 @@ def test_scene_beyond_lds_limit():
     assert sc.n_bodies > 12288
     st, sets, o_prev = _oracle_start(sc, 2, 1)
     w, p = _world(sc)
-    w.write_state(st, keep_cache=False)
-    w.write_cache(o_prev)
-    w.set_load_balance(True, 1, sets=sets)
-    _, o = compare_step(sc, w, p, label="bowl 13000 (global memory)", lb=dict(sets=sets, depth=1))
+    _, o = compare_step(sc, w, p, start=(st, o_prev), label="bowl 13000 (global memory)", lb=dict(sets=sets, depth=1))
     assert int((o["mask"] != sets).sum()) > 0
 
 
@@ -132,8 +127,9 @@ def test_several_scenes():
     sets = oracle.initial_masks(sc)
     w.set_load_balance(True, 0)
     _, o = compare_step(sc, w, p, label="three bowls", lb=dict(sets=sets, depth=0))
-    w.step(1)   # the sets the library carries forward are its own from here
-    _, o2 = compare_step(sc, w, p, label="three bowls, carried", lb=dict(sets=w.debug("mask"), depth=0))
+    # the next step with the sets the library carried from this one
+    _, o2 = compare_step(sc, w, p, start=next_start(o), label="three bowls, carried",
+                         lb=dict(sets=o["mask"].astype(np.uint64), depth=0, carried=True))
 
 
 def test_trajectory_and_graph_replay():
@@ -155,4 +151,7 @@ def test_trajectory_and_graph_replay():
     assert (sets != 0).all()
     load = [int(((sets >> np.uint64(b)) & np.uint64(1)).sum()) for b in range(7)]
     log(f"  bodies per worker after 60 steps {load}")
-    compare_step(sc, w, p, label="bowl 1500 t=61", lb=dict(sets=sets, depth=0))
+    # one step against the oracle from the oracle's own 60-step run
+    ost, oout, _ = oracle.run_lb(sc, 60, 0, dt=sc.dt, max_iters=sc.iters, beta=sc.beta)
+    compare_step(sc, w, p, start=(ost, oout), label="bowl 1500 t=61",
+                 lb=dict(sets=oout["mask"].astype(np.uint64), depth=0))

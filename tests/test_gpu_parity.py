@@ -3,16 +3,22 @@
 Integer results (contacts, graph, masks, replica tables, geodesic distances,
 constraint copies, colours) must match bit for bit; velocities within the
 tolerances of tests/parity.py after one step from the same float32 state.
+Every start is the scene's synthetic initial state or a state and warm-start
+cache the oracle produced; none is read back from the GPU library.
 """
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import paper_2403_17261_amd as ovl
 from paper_2403_17261_amd import scenes
-from parity import check_state, compare_step, log, oracle_kwargs
+from parity import check_state, compare_step, log, next_start, oracle_kwargs, oracle_run
 
 pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def make_world(sc, **pkw):
@@ -38,15 +44,16 @@ def test_config1_first_step():
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_config1_trajectory(seed):
-    """Sampled one-step parity along a 200-step GPU trajectory (warm start on)."""
+    """Sampled one-step parity along a 200-step oracle trajectory (warm start on)."""
     sc = scenes.config1(seed)
     w, p = make_world(sc)
-    t = 0
+    t, start = 0, (sc.state, None)
     for target in (10, 50, 100, 199):
-        w.step(target - t)
+        start = oracle_run(sc, p, target - t, state=start[0], cache=start[1])
         t = target
         log(f"config1 seed {seed} step {t}")
-        compare_step(sc, w, p, label=f"c1 t={t}")
+        _, o = compare_step(sc, w, p, start=start, label=f"c1 t={t}")
+        start = next_start(o)
         t += 1
 
 
@@ -87,9 +94,9 @@ def test_bowl_small_pile():
     sc = scenes.config2(0, n=3000)
     w, p = make_world(sc)
     w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=2, beta=4)
-    w.step(240)
+    start = oracle_run(sc, p, 240, halo_k=2, beta=4)
     log("bowl 3000 step 240")
-    st, o = compare_step(sc, w, p, label="bowl3k t=240")
+    st, o = compare_step(sc, w, p, start=start, halo_k=2, beta=4, label="bowl3k t=240")
     assert st["n_contacts"] > 1000
 
 
@@ -98,47 +105,53 @@ def test_chains_small():
     sc.owner = np.clip(np.floor((sc.state[:, 0] + 20) / 10.0), 0, 3).astype(np.int32)
     sc.parts_per_scene = np.array([4], np.int32)
     w, p = make_world(sc)
-    compare_step(sc, w, p, label="chains t=0")
-    w.step(60)
-    compare_step(sc, w, p, label="chains t=61")
+    _, o = compare_step(sc, w, p, label="chains t=0")
+    s, c = next_start(o)
+    compare_step(sc, w, p, start=oracle_run(sc, p, 60, state=s, cache=c), label="chains t=61")
 
 
 def test_tower_small():
     sc = scenes.config5(1, nx=12, ny=12, nz=8, cols=2)
     w, p = make_world(sc)
-    compare_step(sc, w, p, label="tower t=0")
-    w.step(20)
-    compare_step(sc, w, p, label="tower t=21")
+    _, o = compare_step(sc, w, p, label="tower t=0")
+    s, c = next_start(o)
+    compare_step(sc, w, p, start=oracle_run(sc, p, 20, state=s, cache=c), label="tower t=21")
 
 
 def test_multi_scene_world():
     parts = [scenes.config1(7), scenes.config5(4, nx=6, ny=6, nz=4, cols=2), scenes.config1(8)]
     sc = scenes.concat_scenes(parts, halo_k=2, beta=4, dt=1 / 60, iters=20)
     w, p = make_world(sc)
-    compare_step(sc, w, p, label="3 scenes t=0")
-    w.step(15)
-    compare_step(sc, w, p, label="3 scenes t=16")
+    _, o = compare_step(sc, w, p, label="3 scenes t=0")
+    s, c = next_start(o)
+    compare_step(sc, w, p, start=oracle_run(sc, p, 15, state=s, cache=c), label="3 scenes t=16")
 
 
-def test_adaptive_mode_against_forced_oracle():
-    """Adaptive sweeps: the oracle is run with the GPU's sweep count of every
-    partition (the stop rule is an FP decision); the stop rule itself is
-    checked on the GPU's own residuals."""
+def test_adaptive_mode_against_oracle():
+    """Adaptive sweeps from an oracle-made start.  The stop rule is an FP
+    decision, so each side stops on its own residuals: the GPU's counts are
+    checked against its residuals, and the step is then run again on the GPU
+    with the oracle's sweep count of every partition forced, for the state."""
     sc = scenes.config5(2, nx=10, ny=10, nz=8, cols=2)
     w, p = make_world(sc, mode=ovl.MODE_ADAPTIVE, tol=1e-4)
     w.set_params(max_iters=500)
-    w.step(5)
-    s0 = w.read_state()
-    cache = w.cache()
-    st = w.step(1, stats=True)
+    p = w.params
+    s0, cache = oracle_run(sc, p, 5)
+    w.write_state(s0, keep_cache=False)
+    w.write_cache(cache)
+    w.step(1, stats=True)
     iters = w.debug("part_iters")
     resid = w.debug("part_resid")
     assert np.all((resid <= 1e-4) | (iters == 500))
-    gs = w.read_state()
     kw = oracle_kwargs(sc, p, sc.halo_k, sc.beta)
-    o = oracle.step(sc, state=s0, cache=cache, forced_iters=iters, **kw)
-    log("adaptive iters", iters, "resid", resid)
-    check_state(sc, gs, o["state"], p.dt, "adaptive")
+    o = oracle.step(sc, state=s0, cache=cache, **kw)
+    log("adaptive iters gpu", iters, "oracle", o["part_iters"], "resid", resid)
+    w.write_state(s0, keep_cache=False)
+    w.write_cache(cache)
+    w.force_iters(o["part_iters"])
+    w.step(1, stats=True)
+    w.force_iters(None)
+    check_state(sc, w.read_state(), o["state"], p.dt, "adaptive")
 
 
 def test_nonfinite_step_keeps_state():
@@ -180,10 +193,13 @@ def test_checkpoint_restore_bitwise():
 def test_full_size_sampled(which):
     """Full-size workloads, in the launch configuration the benchmark uses."""
     if which == "bowl20k":
+        # the pile at step 300 as the oracle computed it (oracle/pile_state.py)
+        d = np.load(os.path.join(ROOT, "oracle", "data", "bowl20k_seed0_t300.npz"))
         sc = scenes.config2(0)
         w, p = make_world(sc)
-        w.step(300)
-        compare_step(sc, w, p, label="bowl20k t=300")
+        owner = d["owner"].astype(np.int32)
+        w.set_partitions(owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        compare_step(sc, w, p, start=(d["state"], None), owner=owner, label="bowl20k t=300")
     elif which == "tower100k":
         sc = scenes.config5(0)
         w, p = make_world(sc)
@@ -191,8 +207,7 @@ def test_full_size_sampled(which):
     else:
         sc = scenes.config3(0)
         w, p = make_world(sc)
-        w.step(100)
-        compare_step(sc, w, p, label="chains51k t=100")
+        compare_step(sc, w, p, start=oracle_run(sc, p, 5), label="chains51k t=5")
 
 
 def test_single_colour_partition_keeps_its_impulses():
