@@ -174,3 +174,22 @@ def test_single_partition_is_unchanged():
     cpl = oracle.step(sc, owner=one, parts_per_scene=[1], cache=o0, warmstart=True, coupling=True)
     assert np.array_equal(base["state"], cpl["state"])
     assert np.abs(cpl["rep_cpl"]).max() == 0.0
+
+
+def test_source_is_the_lowest_of_two_partitions_holding_the_pair():
+    # six spheres touching along x, owners 0 0 1 1 2 2, 2-hop overlap: the
+    # contact (3, 4) is solved in partitions 1 and 2 and cut from partition 0
+    # (body 4 is not active there); the impulse stored under partition 1 acts
+    pos = [[0.5 + k, 0, 5] for k in range(6)]
+    sc = scenes.custom_spheres(pos, 0.5, 1.0, owner=[0, 0, 1, 1, 2, 2], n_parts=3, dt=H, iters=0, halo_k=2, beta=4,
+                               mu=0.5)
+    base = oracle.step(sc, halo_k=2, gravity=(0.0, 0.0, 0.0))
+    assert [int(m) for m in base["mask"]] == [3, 3, 7, 7, 6, 6]
+    k34 = [int(k) for k in base["contact_key"] if int(k) >> 32 == 3 and (int(k) >> 1) & 0x7FFFFFFF == 4][0]
+    cache = _cache([(1, 1, k34, (2.0, 0, 0, 0)), (2, 1, k34, (5.0, 0, 0, 0))])
+    o = _run(sc, cache, True, halo_k=2, gravity=(0.0, 0.0, 0.0), adaptive=False,
+             forced_iters=np.array([0, 0, 0], np.int32))
+    # body 3 is body a of the contact: the normal impulse 2 pushes it along -x
+    v = o["rep_state"][_rep(o, 3, 0), 7:10]
+    assert v == pytest.approx([-2.0, 0.0, 0.0], abs=1e-7)
+    assert np.abs(o["rep_cpl"][_rep(o, 3, 1)]).max() == 0.0   # solved in partition 1: nothing cut there
