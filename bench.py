@@ -459,6 +459,9 @@ def main():
                     help="warm start of the timed run; 'both' times plain then learned and reports learned")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2403_17261_amd", "data", "warmstart_mlp.npz"))
     ap.add_argument("--skip-loop", action="store_true", help="batched: leave out the per-scene loop")
+    ap.add_argument("--exact-every", type=int, default=25,
+                    help="tower/bowl: after timing, replay the run untimed with the exact residual every this many "
+                         "steps (0: off)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -537,6 +540,14 @@ def main():
         last = w.step(0, stats=True)
         # untimed: the exact natural-map residual of the step after the timed ones
         nxt = w.step(1, stats=True, exact=True)
+        # untimed: the same run again, the exact residual of every 25th step
+        exact = []
+        if args.exact_every:
+            w.write_state(sc.state, keep_cache=False)
+            w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+            for t in range(args.exact_every, args.steps + 1, args.exact_every):
+                w.step(args.exact_every - 1)
+                exact.append(w.step(1, stats=True, exact=True)["resid_exact"])
         secs = t1 - t0
         steps_done = c1["steps"] - c0["steps"]
         if steps_done != args.steps:
@@ -547,7 +558,8 @@ def main():
              "sweeps_mean": (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / max(1, steps_done),
              "sweeps_part_mean": (c1["sweeps_part_total"] - c0["sweeps_part_total"]) / max(1, steps_done * w.G),
              "unconverged": c1["unconverged_total"] - c0["unconverged_total"], "last": last,
-             "steps_capped": c1["steps_capped"] - c0["steps_capped"], "exact_next": nxt["resid_exact"]}
+             "steps_capped": c1["steps_capped"] - c0["steps_capped"], "exact_next": nxt["resid_exact"],
+             "exact_sampled": exact}
         r["achieved"] = r["pgs_bytes"] / (r["pgs_ms"] * 1e-3) / 1e9 if r["pgs_ms"] > 0 else 0.0
         runs[mode_name] = r
         log(f"[{mode_name}] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step, solver "
@@ -596,7 +608,12 @@ def main():
                                      "partition_sweeps_per_step": round(v["sweeps_part_mean"], 2),
                                      "unconverged_partition_steps": int(v["unconverged"]),
                                      "steps_hitting_cap_pct": round(100.0 * v["steps_capped"] / args.steps, 2),
-                                     "exact_residual_step_after": v["exact_next"]}
+                                     "exact_residual_step_after": v["exact_next"],
+                                     "exact_residual_sampled_mean": (float(np.mean(v["exact_sampled"]))
+                                                                     if v["exact_sampled"] else None),
+                                     "exact_residual_sampled_median": (float(np.median(v["exact_sampled"]))
+                                                                       if v["exact_sampled"] else None),
+                                     "exact_residual_samples": len(v["exact_sampled"])}
                                  for k, v in runs.items()},
             "mean_sweeps_per_step": round(sweeps_mean, 2), "unconverged_partition_steps": int(unconv),
             "last_step": {k: last[k] for k in ("n_contacts", "n_copies", "n_replicas", "n_overlap",
