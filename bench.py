@@ -459,6 +459,8 @@ def main():
                     help="warm start of the timed run; 'both' times plain then learned and reports learned")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2403_17261_amd", "data", "warmstart_mlp.npz"))
     ap.add_argument("--skip-loop", action="store_true", help="batched: leave out the per-scene loop")
+    ap.add_argument("--coupling", action="store_true",
+                    help="tower/bowl: interface coupling by the previous step's impulses of cut constraints")
     ap.add_argument("--exact-every", type=int, default=25,
                     help="tower/bowl: after timing, replay the run untimed with the exact residual every this many "
                          "steps (0: off)")
@@ -504,7 +506,8 @@ def main():
         args.steps = sc.steps
     mode = ovl.MODE_ADAPTIVE if args.mode == "adaptive" else ovl.MODE_FIXED
     cap = args.cap if mode == ovl.MODE_ADAPTIVE else sc.iters
-    p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN)
+    p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN,
+                        coupling=ovl.COUPLING_PREV_IMPULSE if args.coupling else ovl.COUPLING_NONE)
     owner0 = sc.owner.copy()
     cent0 = sc.centroids[0].copy() if sc.rebalance_every else None
     weights = None
@@ -603,6 +606,7 @@ def main():
             "n_bodies": sc.n_bodies, "partitions": int(sc.parts_per_scene[0]), "halo_k": sc.halo_k,
             "beta": sc.beta, "sweeps": f"{args.mode}, tol {args.tol}, cap {cap}",
             "warm_start": "learned (guarded per partition)" if "learned" in runs else "plain",
+            "interface_coupling": bool(args.coupling),
             "learned_vs_plain": {k: {"body_steps_per_s": v["value"], "ms_per_step": v["ms_per_step"],
                                      "sweeps_per_step": round(v["sweeps_mean"], 2),
                                      "partition_sweeps_per_step": round(v["sweeps_part_mean"], 2),
