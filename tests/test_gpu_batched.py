@@ -72,8 +72,8 @@ def test_graph_replays_match_eager_steps():
         a, b = we.read_state(), wg.read_state()         # eager work between the replays
         assert np.array_equal(a, b), chunk
         if chunk == 3:                                   # a parameter change forces a new capture
-            for w in (we, wg):
-                w.set_params(erp=0.25)
+            for w in (we, wg):                           # (and the coupling kernel joins the step)
+                w.set_params(erp=0.25, coupling=ovl.COUPLING_PREV_IMPULSE)
     sa, sb = we.step(1, stats=True), wg.step(1, stats=True)
     assert sa["n_contacts"] == sb["n_contacts"] > 100
     assert np.array_equal(we.read_state(), wg.read_state())
