@@ -210,13 +210,26 @@ def bench_bowl_lb(args):
     p = ovl.make_params(dt=sc.dt, max_iters=args.cap, mode=ovl.MODE_ADAPTIVE, tol=args.tol,
                         warmstart=ovl.WARM_PLAIN)
 
+    p_cpl = ovl.make_params(dt=sc.dt, max_iters=args.cap, mode=ovl.MODE_ADAPTIVE, tol=args.tol,
+                            warmstart=ovl.WARM_PLAIN, coupling=ovl.COUPLING_PREV_IMPULSE)
+
     def restart(w, lb):
         w.write_state(sc.state, keep_cache=False)
         w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=1, beta=sc.beta)
         w.set_load_balance(lb, 0)
 
-    def timed_run(lb):
-        w = ovl.World(sc, p)
+    def exact_replay(w, lb):
+        """The same run again, untimed: the exact residual of every 10th step of its second half."""
+        restart(w, lb)
+        w.step(steps // 2)
+        out = []
+        for _ in range(steps // 2, steps, 10):
+            w.step(9)
+            out.append(float(w.step(1, stats=True, exact=True)["resid_exact"]))
+        return out
+
+    def timed_run(lb, params=p):
+        w = ovl.World(sc, params)
         restart(w, lb)
         log(f"[bowl-lb {'on' if lb else 'off'}] warm-up: the {steps} steps once (buffers grow here)")
         w.step(steps, stats=True)
@@ -266,6 +279,12 @@ def bench_bowl_lb(args):
         return float(np.mean(x.max(axis=1)[ok] / m[ok])) if ok.any() else None
 
     _, off = timed_run(False)
+    w, cpl = timed_run(True, p_cpl)
+    cpl["exact"] = exact_replay(w, True)
+    w.close()
+    w = ovl.World(sc, p)
+    on["exact"] = exact_replay(w, True)
+    w.close()
     pgs_ms, pgs_launches, pgs_bytes = on["pgs_ms"], on["pgs_launches"], on["pgs_bytes"]
     achieved = pgs_bytes / (pgs_ms * 1e-3) / 1e9 if pgs_ms > 0 else 0.0
     cpu = None
@@ -291,6 +310,12 @@ def bench_bowl_lb(args):
             "without_balancing": {"ms_per_step": off["ms_per_step"], "body_steps_per_s": off["value"],
                                   "sweeps_per_step": round(off["sweeps_mean"], 2),
                                   "note": "same owners, 1-hop halo of the naive division every step"},
+            "exact_residual_second_half_mean": float(np.mean(on["exact"])),
+            "with_interface_coupling": {"ms_per_step": cpl["ms_per_step"], "body_steps_per_s": cpl["value"],
+                                        "sweeps_per_step": round(cpl["sweeps_mean"], 2),
+                                        "exact_residual_second_half_mean": float(np.mean(cpl["exact"])),
+                                        "note": "balancing on, plus the previous step's impulses of cut "
+                                                "constraints"},
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
