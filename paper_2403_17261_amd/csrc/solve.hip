@@ -444,7 +444,7 @@ __device__ __forceinline__ void couple_add(const WP& w, int v, f3 F, f3 r, f3& d
   dw = add(dw, inv_inertia(ii, u, dI, cross(r, F)));
 }
 
-__device__ __forceinline__ void couple_contact(const WP& w, int prevM, int pb, uint64_t mv, int v, int c, f3& dv,
+__device__ __forceinline__ bool couple_contact(const WP& w, int prevM, int pb, uint64_t mv, int v, int c, f3& dv,
                                                f3& dw) {
   const int64_t MC = w.Mcap, CC = w.Ccap;
   const int a = w.c_a[c];
@@ -452,9 +452,9 @@ __device__ __forceinline__ void couple_contact(const WP& w, int prevM, int pb, u
   const int b = (int)(bk >> 1);
   const int o = a == v ? b : a;
   const uint64_t both = mv & w.mask[o];
-  if (!both) return;
+  if (!both) return false;
   const int hit = cache_find(w, prevM, pb + __builtin_ctzll(both), 1, ((uint64_t)a << 32) | bk);
-  if (hit < 0) return;
+  if (hit < 0) return false;
   const f3 n = mk(w.c_geom[c], w.c_geom[CC + c], w.c_geom[2 * CC + c]);
   f3 t1, t2;
   tangents(n, t1, t2);
@@ -470,6 +470,7 @@ __device__ __forceinline__ void couple_contact(const WP& w, int prevM, int pb, u
     couple_add(w, v, scale(P, -1.0f), ra, dv, dw);
   else
     couple_add(w, v, P, rb, dv, dw);
+  return true;
 }
 
 __global__ void k_couple(WP w) {
@@ -495,43 +496,56 @@ __global__ void k_couple(WP w) {
   }
   if (!cut) return;
   const int pb = w.s_part_base[w.b_scene[v]];
-  for (uint64_t bits = cut; bits; bits &= bits - 1) {
-    const int i = __builtin_ctzll(bits);
+  // A constraint's impulse on v is found once and added to every replica of
+  // v in whose partition the constraint is cut (cm: those partitions' bits);
+  // each replica's sum still runs in constraint-list order.
+  auto add_to = [&](uint64_t cm, f3 dv, f3 dw) {
+    for (uint64_t bits = cm; bits; bits &= bits - 1) {
+      const int i = __builtin_ctzll(bits);
+      const int r = w.rep_pm_of_bm[bm0 + __popcll(m & ((1ull << i) - 1))];
+      const float4 a = w.rep_cpl[r], b = w.rep_cpl[RC + r];
+      w.rep_cpl[r] = make_float4(a.x + dv.x, a.y + dv.y, a.z + dv.z, 0.0f);
+      w.rep_cpl[RC + r] = make_float4(b.x + dw.x, b.y + dw.y, b.z + dw.z, 0.0f);
+    }
+  };
+  // ball joints (rows along -e_k: the impulse on body a is +lambda)
+  for (int e = w.jinc_off[v]; e < w.jinc_off[v + 1]; ++e) {
+    const int j = w.jinc[e];
+    const int ja = w.j_ab[2 * j], jb = w.j_ab[2 * j + 1];
+    const int o = ja == v ? jb : ja;
+    const uint64_t mo = w.mask[o], cm = m & ~mo, both = m & mo;
+    if (!cm || !both) continue;
+    const int hit = cache_find(w, prevM, pb + __builtin_ctzll(both), 0, (uint64_t)j);
+    if (hit < 0) continue;
+    const int64_t MC = w.Mcap;
+    const f3 lam = mk(w.wc_val[hit], w.wc_val[MC + hit], w.wc_val[2 * MC + hit]);
+    const float* an = w.j_anchor + 6 * j + (ja == v ? 0 : 3);
+    const f3 r = quat_rotate(w.st[3 * N + v], w.st[4 * N + v], w.st[5 * N + v], w.st[6 * N + v],
+                             mk(an[0], an[1], an[2]));
     f3 dv = mk(0.0f, 0.0f, 0.0f), dw = mk(0.0f, 0.0f, 0.0f);
-    // ball joints (rows along -e_k: the impulse on body a is +lambda)
-    for (int e = w.jinc_off[v]; e < w.jinc_off[v + 1]; ++e) {
-      const int j = w.jinc[e];
-      const int ja = w.j_ab[2 * j], jb = w.j_ab[2 * j + 1];
-      const int o = ja == v ? jb : ja;
-      if (w.mask[o] >> i & 1) continue;
-      const uint64_t both = m & w.mask[o];
-      if (!both) continue;
-      const int hit = cache_find(w, prevM, pb + __builtin_ctzll(both), 0, (uint64_t)j);
-      if (hit < 0) continue;
-      const int64_t MC = w.Mcap;
-      const f3 lam = mk(w.wc_val[hit], w.wc_val[MC + hit], w.wc_val[2 * MC + hit]);
-      const float* an = w.j_anchor + 6 * j + (ja == v ? 0 : 3);
-      const f3 r = quat_rotate(w.st[3 * N + v], w.st[4 * N + v], w.st[5 * N + v], w.st[6 * N + v],
-                               mk(an[0], an[1], an[2]));
-      couple_add(w, v, ja == v ? lam : scale(lam, -1.0f), r, dv, dw);
-    }
-    // contacts whose body a is a smaller neighbour u (adjacency is sorted, -1 padded)
-    for (int k = a0; k < a1; ++k) {
-      const int u = w.adj[k];
-      if (u < 0 || u >= v) break;
-      if (w.mask[u] >> i & 1) continue;
-      for (int c = w.coff[u]; c < w.coff[u + 1]; ++c)
-        if ((w.c_bkey[c] >> 1) == (uint32_t)v) couple_contact(w, prevM, pb, m, v, c, dv, dw);
-    }
-    // contacts whose body a is v
-    for (int c = w.coff[v]; c < w.coff[v + 1]; ++c) {
-      const uint32_t o = w.c_bkey[c] >> 1;
-      if (o >= (uint32_t)N || (w.mask[o] >> i & 1)) continue;
-      couple_contact(w, prevM, pb, m, v, c, dv, dw);
-    }
-    const int r = w.rep_pm_of_bm[bm0 + __popcll(m & ((1ull << i) - 1))];
-    w.rep_cpl[r] = make_float4(dv.x, dv.y, dv.z, 0.0f);
-    w.rep_cpl[RC + r] = make_float4(dw.x, dw.y, dw.z, 0.0f);
+    couple_add(w, v, ja == v ? lam : scale(lam, -1.0f), r, dv, dw);
+    add_to(cm, dv, dw);
+  }
+  // contacts whose body a is a smaller neighbour u (adjacency is sorted, -1 padded)
+  for (int k = a0; k < a1; ++k) {
+    const int u = w.adj[k];
+    if (u < 0 || u >= v) break;
+    const uint64_t cm = m & ~w.mask[u];
+    if (!cm) continue;
+    for (int c = w.coff[u]; c < w.coff[u + 1]; ++c)
+      if ((w.c_bkey[c] >> 1) == (uint32_t)v) {
+        f3 dv = mk(0.0f, 0.0f, 0.0f), dw = mk(0.0f, 0.0f, 0.0f);
+        if (couple_contact(w, prevM, pb, m, v, c, dv, dw)) add_to(cm, dv, dw);
+      }
+  }
+  // contacts whose body a is v
+  for (int c = w.coff[v]; c < w.coff[v + 1]; ++c) {
+    const uint32_t o = w.c_bkey[c] >> 1;
+    if (o >= (uint32_t)N) continue;
+    const uint64_t cm = m & ~w.mask[o];
+    if (!cm) continue;
+    f3 dv = mk(0.0f, 0.0f, 0.0f), dw = mk(0.0f, 0.0f, 0.0f);
+    if (couple_contact(w, prevM, pb, m, v, c, dv, dw)) add_to(cm, dv, dw);
   }
 }
 
