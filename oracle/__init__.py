@@ -200,7 +200,9 @@ def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced
     if p["forced_guard"] is not None:
         pr.forced_guard = _ptr(arr(p["forced_guard"], np.int32))
     pr.equal_weights = int(bool(p["equal_weights"]))
-    pr.coupling = int(bool(p["coupling"]))
+    pr.coupling = int(p["coupling"])  # 0 none, 1 previous-step impulses, 2 mass splitting
+    if pr.coupling not in (0, 1, 2):
+        raise ValueError("coupling must be 0, 1 or 2")
     if p["lb_masks"] is not None:
         pr.lb_masks = _ptr(arr(p["lb_masks"], np.uint64))
         pr.lb_depth = int(p["lb_depth"])

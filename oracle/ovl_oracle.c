@@ -1094,7 +1094,11 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
       q->w[k] = s[10 + k];
     }
     for (int k = 0; k < 4; ++k) q->q[k] = s[3 + k];
-    q->invm = 1.0 / (double)sc->mass[v];
+    /* mass splitting: the replica carries the share w of the body (inverse
+     * mass and inverse inertia over w); weight 0 keeps the whole body */
+    double share = 1.0;
+    if (prm->coupling == 2 && repW[r] > 0.0) share = repW[r];
+    q->invm = 1.0 / (double)sc->mass[v] / share;
     double Rm[9], Ib[3];
     quat_to_mat(q->q, Rm);
     for (int k = 0; k < 3; ++k) Ib[k] = 1.0 / (double)sc->inertia[3 * v + k];
@@ -1102,7 +1106,7 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
       for (int j = 0; j < 3; ++j) {
         double acc = 0;
         for (int k = 0; k < 3; ++k) acc += Rm[3 * i + k] * Ib[k] * Rm[3 * j + k];
-        q->invi[3 * i + j] = acc;
+        q->invi[3 * i + j] = acc / share;
       }
     /* Eq. 1 with f = m g: v~ = v + h g */
     q->v[0] += h * prm->gx;
@@ -1192,7 +1196,7 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
    * (the signs of the rows' impulses). ---- */
   for (int64_t r = 0; r < R; ++r)
     for (int k = 0; k < 6; ++k) rep[r].cpl[k] = 0.0;
-  if (prm->coupling && cache && cache->n > 0) {
+  if (prm->coupling == 1 && cache && cache->n > 0) {
     /* incidence lists: body -> constraints (joints first, then contacts) */
     int64_t* ioff = (int64_t*)xalloc((size_t)(N + 1) * 8);
     for (int64_t v = 0; v <= N; ++v) ioff[v] = 0;

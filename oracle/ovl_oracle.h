@@ -63,7 +63,14 @@ typedef struct {
    * the partition with the lowest id among those active in both bodies left
    * it (cache key as for the warm start, friction carried as a world vector,
    * projected and clipped as the warm start does), acts on the body inside
-   * P_i as a fixed impulse added to its free velocity before the solve. */
+   * P_i as a fixed impulse added to its free velocity before the solve.
+   * 2: mass splitting at the interface (section 2 relates the blend to the
+   * mass splitting of [TBV12]: the workers share a body's mass).  The replica
+   * of an overlap body in partition i carries the share w_i of its mass and
+   * of its inertia (inverse mass and inverse inertia divided by its blend
+   * weight w_i; a replica of weight 0 keeps the whole body), so that the
+   * blend sum_i w_i v_i equals the body's free velocity plus the sum of the
+   * partitions' impulses applied to the whole body. */
   int32_t coupling;
 } orc_params;
 
