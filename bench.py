@@ -21,9 +21,10 @@ and contact distributions over the run and the same run without balancing.
 chains of 200 ball-jointed spheres over 16 static spheres, 16 x-slabs, h
 1/120 s, 40 sweeps, 500 steps, seeds 0-2): overlap depth k = 1..4 (gamma = k - 1) with
 geodesic and with equal blend weights, with geodesic weights plus interface
-coupling by the previous step's impulses of cut constraints (section 7), and
-one partition as the reference; joint violation and total residual sampled
-every 25 steps.
+coupling by the previous step's impulses of cut constraints (section 7) or by
+splitting the mass of overlap bodies by blend weight (section 2's comparison
+with mass splitting), and one partition as the reference; joint violation and
+total residual sampled every 25 steps.
 
 --workload batched: 512 independent bowl scenes (log-uniform 200..5000
 spheres, 1..6 k-means partitions each, fixed at the start), 30 sweeps per
@@ -49,6 +50,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# interface coupling modes (the library's OVL_COUPLING_* values)
+COUPLING_NAMES = {0: "none", 1: "previous-step impulses", 2: "mass splitting"}
+COUPLING_FLAGS = {"none": 0, "impulse": 1, "split": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pgs_traffic.json")
 SOLVER_SRC = os.path.join(ROOT, "paper_2403_17261_amd", "csrc", "solve.hip")
 
@@ -212,6 +216,8 @@ def bench_bowl_lb(args):
 
     p_cpl = ovl.make_params(dt=sc.dt, max_iters=args.cap, mode=ovl.MODE_ADAPTIVE, tol=args.tol,
                             warmstart=ovl.WARM_PLAIN, coupling=ovl.COUPLING_PREV_IMPULSE)
+    p_split = ovl.make_params(dt=sc.dt, max_iters=args.cap, mode=ovl.MODE_ADAPTIVE, tol=args.tol,
+                              warmstart=ovl.WARM_PLAIN, coupling=ovl.COUPLING_MASS_SPLIT)
 
     def restart(w, lb):
         w.write_state(sc.state, keep_cache=False)
@@ -282,6 +288,9 @@ def bench_bowl_lb(args):
     w, cpl = timed_run(True, p_cpl)
     cpl["exact"] = exact_replay(w, True)
     w.close()
+    w, split = timed_run(True, p_split)
+    split["exact"] = exact_replay(w, True)
+    w.close()
     w = ovl.World(sc, p)
     on["exact"] = exact_replay(w, True)
     w.close()
@@ -316,6 +325,11 @@ def bench_bowl_lb(args):
                                         "exact_residual_second_half_mean": float(np.mean(cpl["exact"])),
                                         "note": "balancing on, plus the previous step's impulses of cut "
                                                 "constraints"},
+            "with_mass_splitting": {"ms_per_step": split["ms_per_step"], "body_steps_per_s": split["value"],
+                                    "sweeps_per_step": round(split["sweeps_mean"], 2),
+                                    "exact_residual_second_half_mean": float(np.mean(split["exact"])),
+                                    "note": "balancing on, overlap replicas carry their blend weight's share of "
+                                            "the body's mass and inertia"},
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -331,7 +345,7 @@ def bench_bowl_lb(args):
 
 def bench_accuracy(args):
     """Section 6's error measures on the chains, seeds 0-2: geodesic against equal
-    weights, the overlap depth, and interface coupling."""
+    weights, the overlap depth, and the two interface couplings."""
     import torch
 
     import paper_2403_17261_amd as ovl
@@ -339,9 +353,10 @@ def bench_accuracy(args):
 
     seeds = tuple(int(x) for x in args.seeds.split(","))
     every = 25
-    # (overlap depth k, blend weights, interface coupling); k = 0: one partition
-    variants = ([(k, wmode, False) for k in (1, 2, 3, 4) for wmode in ("geodesic", "equal")] +
-                [(k, "geodesic", True) for k in (1, 2, 3, 4)] + [(0, "one partition", False)])
+    # (overlap depth k, blend weights, interface coupling mode); k = 0: one partition
+    variants = ([(k, wmode, ovl.COUPLING_NONE) for k in (1, 2, 3, 4) for wmode in ("geodesic", "equal")] +
+                [(k, "geodesic", c) for c in (ovl.COUPLING_PREV_IMPULSE, ovl.COUPLING_MASS_SPLIT)
+                 for k in (1, 2, 3, 4)] + [(0, "one partition", ovl.COUPLING_NONE)])
     per_seed = {v: [] for v in variants}
     steps = None
     for seed in seeds:
@@ -350,7 +365,7 @@ def bench_accuracy(args):
         for k, wmode, cpl in variants:
             p = ovl.make_params(dt=sc.dt, max_iters=sc.iters, mode=ovl.MODE_FIXED, warmstart=ovl.WARM_PLAIN,
                                 weights=ovl.WEIGHTS_EQUAL if wmode == "equal" else ovl.WEIGHTS_GEODESIC,
-                                coupling=ovl.COUPLING_PREV_IMPULSE if cpl else ovl.COUPLING_NONE)
+                                coupling=cpl)
             w = ovl.World(sc, p)
             if k == 0:
                 w.set_partitions(np.zeros(sc.n_bodies, np.int32), np.array([1], np.int32), halo_k=1, beta=sc.beta)
@@ -376,7 +391,7 @@ def bench_accuracy(args):
                  "total_residual_mean_second_half": float(half[:, 3].mean()),
                  "overlap_bodies_mean": float(a[:, 5].mean()), "replicas_mean": float(a[:, 6].mean())}
             per_seed[(k, wmode, cpl)].append(r)
-            log(f"[accuracy seed {seed} k={k} {wmode}{' coupled' if cpl else ''}] joint violation sum "
+            log(f"[accuracy seed {seed} k={k} {wmode} {COUPLING_NAMES[cpl]}] joint violation sum "
                 f"{r['joint_violation_sum_mean_second_half']:.4e} m (max {r['joint_violation_max_mean_second_half']:.3e}), "
                 f"total residual {r['total_residual_mean_second_half']:.4e} m/s, overlap "
                 f"{r['overlap_bodies_mean']:.0f}, {r['ms_per_step']:.2f} ms/step")
@@ -384,7 +399,7 @@ def bench_accuracy(args):
     keys = ("ms_per_step", "joint_violation_sum_mean_second_half", "joint_violation_max_mean_second_half",
             "joint_violation_max_worst", "total_residual_mean_second_half", "overlap_bodies_mean", "replicas_mean")
     for (k, wmode, cpl), rs in per_seed.items():
-        r = {"k": k, "weights": wmode, "coupling": "previous-step impulses" if cpl else "none"}
+        r = {"k": k, "weights": wmode, "coupling": COUPLING_NAMES[cpl]}
         for key in keys:
             vals = [x[key] for x in rs]
             r[key] = float(np.max(vals)) if key == "joint_violation_max_worst" else float(np.mean(vals))
@@ -485,8 +500,9 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2403_17261_amd", "data", "warmstart_mlp.npz"))
     ap.add_argument("--skip-loop", action="store_true", help="batched: leave out the per-scene loop")
     ap.add_argument("--seeds", default="0,1,2", help="accuracy: scene seeds, comma-separated")
-    ap.add_argument("--coupling", action="store_true",
-                    help="tower/bowl: interface coupling by the previous step's impulses of cut constraints")
+    ap.add_argument("--coupling", nargs="?", const="impulse", default="none", choices=["none", "impulse", "split"],
+                    help="tower/bowl: interface coupling, by the previous step's impulses of cut constraints "
+                         "(impulse) or by splitting the mass of overlap bodies (split)")
     ap.add_argument("--exact-every", type=int, default=25,
                     help="tower/bowl: after timing, replay the run untimed with the exact residual every this many "
                          "steps (0: off)")
@@ -533,7 +549,7 @@ def main():
     mode = ovl.MODE_ADAPTIVE if args.mode == "adaptive" else ovl.MODE_FIXED
     cap = args.cap if mode == ovl.MODE_ADAPTIVE else sc.iters
     p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN,
-                        coupling=ovl.COUPLING_PREV_IMPULSE if args.coupling else ovl.COUPLING_NONE)
+                        coupling=COUPLING_FLAGS[args.coupling])
     owner0 = sc.owner.copy()
     cent0 = sc.centroids[0].copy() if sc.rebalance_every else None
     weights = None
@@ -632,7 +648,7 @@ def main():
             "n_bodies": sc.n_bodies, "partitions": int(sc.parts_per_scene[0]), "halo_k": sc.halo_k,
             "beta": sc.beta, "sweeps": f"{args.mode}, tol {args.tol}, cap {cap}",
             "warm_start": "learned (guarded per partition)" if "learned" in runs else "plain",
-            "interface_coupling": bool(args.coupling),
+            "interface_coupling": COUPLING_NAMES[COUPLING_FLAGS[args.coupling]],
             "learned_vs_plain": {k: {"body_steps_per_s": v["value"], "ms_per_step": v["ms_per_step"],
                                      "sweeps_per_step": round(v["sweeps_mean"], 2),
                                      "partition_sweeps_per_step": round(v["sweeps_part_mean"], 2),

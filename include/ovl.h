@@ -91,8 +91,17 @@ enum { OVL_WEIGHTS_GEODESIC = 0, OVL_WEIGHTS_EQUAL = 1 };
  * warm start's key; a contact's friction is carried as a world vector,
  * projected on the new tangents and clipped to the new friction box, its
  * normal impulse clamped to >= 0); none if that partition did not solve it
- * then.  The features of the learned warm start see the coupled velocity. */
-enum { OVL_COUPLING_NONE = 0, OVL_COUPLING_PREV_IMPULSE = 1 };
+ * then.  The features of the learned warm start see the coupled velocity.
+ * OVL_COUPLING_MASS_SPLIT: the workers share the mass of an overlap body
+ * (section 2 relates the blend to the mass splitting of [TBV12]).  The
+ * replica of an overlap body in partition i carries the share w_i of the
+ * body's mass and inertia, w_i being its blend weight (inverse mass and
+ * inverse inertia divided by w_i; a replica of weight 0 keeps the whole
+ * body), in the rows, the sweeps, the residuals and the learned features.
+ * The blend sum_i w_i v_i then applies the sum of the partitions' impulses
+ * to the whole body, so a partitioned step conserves momentum where the
+ * constraint impulses are equal and opposite. */
+enum { OVL_COUPLING_NONE = 0, OVL_COUPLING_PREV_IMPULSE = 1, OVL_COUPLING_MASS_SPLIT = 2 };
 
 /* Parameters of the warm-start network 12 -> 64 -> 64 -> 3 (ReLU), flat:
  * W1[12][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3], input index first. */

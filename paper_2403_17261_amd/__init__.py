@@ -23,7 +23,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_CAPACITY, ERR_NONFINITE, ERR_DEVICE, NOT_CONVE
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "CAPACITY", 4: "NONFINITE", 5: "DEVICE", 6: "NOT_CONVERGED"}
 MODE_FIXED, MODE_ADAPTIVE = 0, 1
 WEIGHTS_GEODESIC, WEIGHTS_EQUAL = 0, 1
-COUPLING_NONE, COUPLING_PREV_IMPULSE = 0, 1
+COUPLING_NONE, COUPLING_PREV_IMPULSE, COUPLING_MASS_SPLIT = 0, 1, 2
 WARM_NONE, WARM_PLAIN, WARM_LEARNED = 0, 1, 2
 MLP_PARAMS = 5187
 

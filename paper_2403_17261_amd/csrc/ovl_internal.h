@@ -62,6 +62,7 @@ struct WP {
   int32_t max_iters, adaptive, warmstart, halo_k, beta;
   int32_t equal_w;               // 1: equal blend weights instead of geodesic ones
   int32_t couple;                // 1: previous-step impulses of cut constraints act on the partition's bodies
+  int32_t msplit;                // 1: an overlap replica carries the share w of its body's mass and inertia
   uint32_t seed;
   int32_t forced;                // 1: part_force_iters holds each partition's sweep count
   // static body data
@@ -161,6 +162,7 @@ struct WP {
   int2* r_ids;                  // [Mcap] (local replica a | kJointFlag | kGenFlag, local replica b or -1)
   float4* rep_ax;               // [Rcap] capsule axis u and 1/I_axis - 1/I_perp of each replica
   float4* rep_cpl;              // [2*Rcap] interface-coupling impulse per replica: (dv, 0), then (dw, 0)
+  float* rep_isc;               // [Rcap] mass splitting: inverse mass and inertia factor 1/w per replica
   float4* r_lam;                // [Mcap] impulses (3 used)
   float4* r_lam0;               // [Mcap] warm-start impulses
   float4* rep_v4;               // [2*Rcap] velocity storage of partitions too large for LDS

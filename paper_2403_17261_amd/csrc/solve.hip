@@ -96,6 +96,28 @@ __device__ __forceinline__ f3 inv_inertia(float ii, f3 u, float dI, f3 x) {
   return add(scale(x, ii), scale(u, dI * dot(u, x)));
 }
 
+// Blend weight (Eq. 15-16) of a replica at geodesic distance D of a body in
+// n > 1 partitions, given the sum of 1/D over the body's replicas: 1/D
+// normalised, uniform where no search reached a partition or with equal weights.
+__device__ __forceinline__ float inv_dist_sum(const WP& w, int bm0, int n) {
+  float sum = 0.0f;
+  for (int k = 0; k < n; ++k) {
+    const int D = w.rep_D_bm[bm0 + k];
+    sum += D > 0 ? 1.0f / (float)D : 0.0f;
+  }
+  return sum;
+}
+
+__device__ __forceinline__ float blend_weight(const WP& w, int D, float sum, int n) {
+  return (sum > 0.0f && !w.equal_w) ? (D > 0 ? 1.0f / (float)D : 0.0f) / sum : 1.0f / (float)n;
+}
+
+// mass splitting: factor on the inverse mass and inverse inertia of the
+// replica with local index r of partition p (1 without splitting)
+__device__ __forceinline__ float rep_split(const WP& w, int p, int r) {
+  return w.msplit ? w.rep_isc[w.part_rep_off[p] + r] : 1.0f;
+}
+
 // lever arms of contact c: r_a = s_a u_a + l_a n, r_b = t_b u_b - l_b n
 __device__ __forceinline__ void contact_arms(const WP& w, int c, int a, int b, f3 n, f3& ra, f3& rb) {
   const int64_t CC = w.Ccap;
@@ -585,7 +607,7 @@ __device__ void write_features(const WP& w, int u, int src, int p, float l0, flo
   }
   f3 pa = add(va, cross(wa, ra));
   f3 pb = mk(0, 0, 0);
-  const float ima = w.b_invm[a];
+  const float ima = w.b_invm[a] * rep_split(w, p, w.cp_ia[u]);
   float imb = 0.0f;
   if (b >= 0) {
     f3 vb = add(mk(w.st[7 * N + b], w.st[8 * N + b], w.st[9 * N + b]), hg);
@@ -596,7 +618,7 @@ __device__ void write_features(const WP& w, int u, int src, int p, float l0, flo
       wb = add(wb, mk(cw.x, cw.y, cw.z));
     }
     pb = add(vb, cross(wb, rb));
-    imb = w.b_invm[b];
+    imb = w.b_invm[b] * rep_split(w, p, w.cp_ib[u]);
   }
   const f3 vr = sub(pb, pa);
   const float g = sqrtf(w.gx * w.gx + w.gy * w.gy + w.gz * w.gz);
@@ -659,7 +681,8 @@ __global__ void k_rows(WP w) {
     const f3 dx = mk(w.st[a] - w.st[b], w.st[N + a] - w.st[N + b], w.st[2 * N + a] - w.st[2 * N + b]);
     const f3 C = add(dx, sub(ra, rb));
     const float k = w.erp / w.dt;
-    const float ima = w.b_invm[a], iia = w.b_invI[a], imb = w.b_invm[b], iib = w.b_invI[b];
+    const float sa = rep_split(w, p, w.cp_ia[u]), sb = rep_split(w, p, w.cp_ib[u]);
+    const float ima = w.b_invm[a] * sa, iia = w.b_invI[a] * sa, imb = w.b_invm[b] * sb, iib = w.b_invI[b] * sb;
     float Ax, Ay, Az;
     const bool gen = w.has_caps && (w.b_half[a] > 0.0f || w.b_half[b] > 0.0f);
     if (!gen) {
@@ -670,7 +693,7 @@ __global__ void k_rows(WP w) {
       Az = ima + imb + iia * (raa - ra.z * ra.z) + iib * (rbb - rb.z * rb.z) + w.cfm;
     } else {
       const f3 ua = body_axis(w, a), ub = body_axis(w, b);
-      const float dIa = w.b_dI[a], dIb = w.b_dI[b];
+      const float dIa = w.b_dI[a] * sa, dIb = w.b_dI[b] * sb;
       float Ak[3];
       for (int e = 0; e < 3; ++e) {
         const f3 ek = mk(e == 0 ? 1.0f : 0.0f, e == 1 ? 1.0f : 0.0f, e == 2 ? 1.0f : 0.0f);
@@ -707,8 +730,9 @@ __global__ void k_rows(WP w) {
     if (b < 0) atomicAdd(&w.part_nstatic[p], 1);
     const float bias = phi > 0.0f ? phi / w.dt : w.erp * phi / w.dt;
     const float mu = w.s_mu[w.b_scene[a]];
-    const float ima = w.b_invm[a], iia = w.b_invI[a];
-    const float imb = b >= 0 ? w.b_invm[b] : 0.0f, iib = b >= 0 ? w.b_invI[b] : 0.0f;
+    const float sa = rep_split(w, p, w.cp_ia[u]), sb = b >= 0 ? rep_split(w, p, w.cp_ib[u]) : 0.0f;
+    const float ima = w.b_invm[a] * sa, iia = w.b_invI[a] * sa;
+    const float imb = b >= 0 ? w.b_invm[b] * sb : 0.0f, iib = b >= 0 ? w.b_invI[b] * sb : 0.0f;
     const bool gen = w.has_caps && (w.b_half[a] > 0.0f || (b >= 0 && w.b_half[b] > 0.0f));
     if (!gen) {
       // sphere contact: r_a = l_a n, r_b = -l_b n, so r x n = 0 and |r x t|^2 = l^2
@@ -724,7 +748,7 @@ __global__ void k_rows(WP w) {
       contact_arms(w, c, a, b, n, ra, rb);
       if (b < 0) rb = mk(0.0f, 0.0f, 0.0f);
       const f3 ua = body_axis(w, a), ub = b >= 0 ? body_axis(w, b) : mk(0.0f, 0.0f, 0.0f);
-      const float dIa = w.b_dI[a], dIb = b >= 0 ? w.b_dI[b] : 0.0f;
+      const float dIa = w.b_dI[a] * sa, dIb = b >= 0 ? w.b_dI[b] * sb : 0.0f;
       const f3 dirs[3] = {n, t1, t2};
       float Ad[3];
       for (int e = 0; e < 3; ++e) {
@@ -1028,15 +1052,17 @@ __device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, i
 }
 
 // replica velocities with gravity applied (v~ = v + h g), plus the interface
-// coupling impulse when that option is on, and inverse masses
+// coupling impulse when that option is on, and inverse masses (the replica's
+// share of them under mass splitting)
 template <int BS>
 __device__ void load_replicas(const WP& w, Vel V, int r0, int nr) {
   const int N = w.N;
   const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
   for (int r = threadIdx.x; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
-    float4 lin = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b]);
-    float4 ang = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b]);
+    const float sp = w.msplit ? w.rep_isc[r0 + r] : 1.0f;
+    float4 lin = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b] * sp);
+    float4 ang = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b] * sp);
     if (w.couple) {
       const float4 cv = w.rep_cpl[r0 + r], cw = w.rep_cpl[w.Rcap + r0 + r];
       lin.x += cv.x;
@@ -1330,6 +1356,25 @@ __global__ __launch_bounds__(kOrderBS) void k_part_order(WP w) {
   }
 }
 
+// Mass splitting: every replica of an overlap body carries the share w of the
+// body that the blend will give it; its inverse mass and inertia are divided
+// by w (a replica of weight 0 keeps the whole body).
+__global__ void k_mass_split(WP w) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= w.N || step_failed(w)) return;
+  const int n = __popcll(w.mask[v]);
+  const int bm0 = w.rep_off_bm[v];
+  if (n == 1) {
+    w.rep_isc[w.rep_pm_of_bm[bm0]] = 1.0f;
+    return;
+  }
+  const float sum = inv_dist_sum(w, bm0, n);
+  for (int k = 0; k < n; ++k) {
+    const float wt = blend_weight(w, w.rep_D_bm[bm0 + k], sum, n);
+    w.rep_isc[w.rep_pm_of_bm[bm0 + k]] = wt > 0.0f ? 1.0f / wt : 1.0f;
+  }
+}
+
 // capsule axis and inertia difference of every replica (read by capsule rows)
 __global__ void k_rep_axis(WP w) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1338,7 +1383,7 @@ __global__ void k_rep_axis(WP w) {
   float4 ax = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if (w.b_half[b] > 0.0f) {
     const f3 u = body_axis(w, b);
-    ax = make_float4(u.x, u.y, u.z, w.b_dI[b]);
+    ax = make_float4(u.x, u.y, u.z, w.b_dI[b] * (w.msplit ? w.rep_isc[r] : 1.0f));
   }
   w.rep_ax[r] = ax;
 }
@@ -1360,18 +1405,13 @@ __global__ void k_blend(WP w) {
     w.rep_w_bm[bm0] = 1.0f;
     return;
   }
-  float sum = 0.0f;
-  for (int k = 0; k < n; ++k) {
-    const int D = w.rep_D_bm[bm0 + k];
-    sum += D > 0 ? 1.0f / (float)D : 0.0f;
-  }
+  const float sum = inv_dist_sum(w, bm0, n);
   float acc[13];
 #pragma unroll
   for (int k = 0; k < 13; ++k) acc[k] = 0.0f;
   float q0[4];
   for (int k = 0; k < n; ++k) {
-    const int D = w.rep_D_bm[bm0 + k];
-    const float wt = (sum > 0.0f && !w.equal_w) ? (D > 0 ? 1.0f / (float)D : 0.0f) / sum : 1.0f / (float)n;
+    const float wt = blend_weight(w, w.rep_D_bm[bm0 + k], sum, n);
     w.rep_w_bm[bm0 + k] = wt;
     const int r = w.rep_pm_of_bm[bm0 + k];
     float s[13];
@@ -1760,6 +1800,10 @@ hipError_t launch_solve_pre(const WP& w, hipStream_t s) {
   hipError_t e;
   if (w.couple && w.N > 0) {
     k_couple<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+  }
+  if (w.msplit && w.N > 0) {
+    k_mass_split<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
   if (w.G > 0) {

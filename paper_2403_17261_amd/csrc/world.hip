@@ -160,6 +160,7 @@ struct ovl_world {
     w.r_gen = alloc<float4>(g, w.has_caps ? (size_t)2 * Mcap : 1, ok);
     w.rep_ax = alloc<float4>(g, w.has_caps ? (size_t)Rcap : 1, ok);
     w.rep_cpl = alloc<float4>(g, (size_t)2 * Rcap, ok);
+    w.rep_isc = alloc<float>(g, Rcap, ok);
     w.r_ids = alloc<int2>(g, Mcap, ok);
     w.r_lam = alloc<float4>(g, Mcap, ok);
     w.r_lam0 = alloc<float4>(g, Mcap, ok);
@@ -238,6 +239,7 @@ struct ovl_world {
     wp.seed = p.seed;
     wp.equal_w = p.weights == OVL_WEIGHTS_EQUAL ? 1 : 0;
     wp.couple = p.coupling == OVL_COUPLING_PREV_IMPULSE ? 1 : 0;
+    wp.msplit = p.coupling == OVL_COUPLING_MASS_SPLIT ? 1 : 0;
   }
 
   bool read_scal(int32_t* out) {
@@ -370,7 +372,9 @@ ovl_status validate_params(const ovl_params* p, std::string& err) {
   else if (p->warmstart != OVL_WARM_NONE && p->warmstart != OVL_WARM_PLAIN) err = "bad warmstart mode";
   else if (!(p->tol >= 0.0f)) err = "tol must be >= 0";
   else if (p->weights != OVL_WEIGHTS_GEODESIC && p->weights != OVL_WEIGHTS_EQUAL) err = "bad weights mode";
-  else if (p->coupling != OVL_COUPLING_NONE && p->coupling != OVL_COUPLING_PREV_IMPULSE) err = "bad coupling mode";
+  else if (p->coupling != OVL_COUPLING_NONE && p->coupling != OVL_COUPLING_PREV_IMPULSE &&
+           p->coupling != OVL_COUPLING_MASS_SPLIT)
+    err = "bad coupling mode";
   else if (!std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2]))
     err = "gravity must be finite";
   else

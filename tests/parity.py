@@ -35,7 +35,7 @@ def oracle_kwargs(sc, params, halo_k, beta):
     return dict(dt=params.dt, gravity=tuple(params.gravity), cfm=params.cfm, erp=params.erp,
                 max_iters=params.max_iters, tol=params.tol, adaptive=params.mode == 1,
                 warmstart=params.warmstart == 1, seed=params.seed, halo_k=halo_k, beta=beta,
-                equal_weights=params.weights == 1, coupling=params.coupling == 1)
+                equal_weights=params.weights == 1, coupling=int(params.coupling))
 
 
 def check_state(sc, gpu, ref, dt, label=""):
@@ -143,7 +143,7 @@ def compare_step(sc, w, params, start=None, owner=None, pps=None, halo_k=None, b
             log(f"  warm start: {len(bad)} copies beyond {1e-5 * scale:.3e}; first uid {u} kind {g['copy_kind'][u]} "
                 f"key {int(g['copy_key'][u]):#x} gpu {g['copy_lambda0'][u]} oracle {o['copy_lambda0'][u]}")
         assert d0 <= 1e-5 * scale, f"warm start differs by {d0}"
-    if params.coupling:
+    if params.coupling == 1:
         # interface-coupling impulses per replica: float32 sums of a few
         # float32 impulses against the oracle's double ones
         gc, oc = w.debug("rep_cpl").astype(np.float64), o["rep_cpl"]

@@ -100,7 +100,7 @@ def test_create_world_rejects_bad_input_before_touching_the_device(what, over):
 
 
 @pytest.mark.parametrize("field,val", [("dt", 0.0), ("erp", 1.5), ("max_iters", 0), ("mode", 7), ("cfm", -1.0),
-                                       ("weights", 2), ("coupling", 2), ("coupling", -1)])
+                                       ("weights", 2), ("coupling", 3), ("coupling", -1)])
 def test_create_world_rejects_bad_params(field, val):
     sc = scenes.config1(0)
     d, keep = _desc_with(sc)

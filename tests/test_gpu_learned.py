@@ -62,16 +62,18 @@ def test_mlp_bf16_inference_matches_oracle():
     assert err.max() < 2e-2
 
 
-@pytest.mark.parametrize("which, coupled", [("lattice", False), ("tower", False), ("lattice", True), ("tower", True)])
+@pytest.mark.parametrize("which, coupled", [("lattice", 0), ("tower", 0), ("lattice", 1), ("tower", 1), ("lattice", 2),
+                                           ("tower", 2)])
 def test_learned_step_matches_oracle(which, coupled):
-    """With interface coupling on, the features see the coupled free velocity."""
+    """With interface coupling on, the features see the coupled free velocity;
+    with mass splitting, the replicas' shares of the inverse masses."""
     if which == "lattice":
         sc = scenes.config1(3)
     else:
         sc = scenes.config5(2, nx=10, ny=10, nz=6, cols=2)
     P = scenes.mlp_initial_weights(11) * np.float32(0.3)
     p = ovl.make_params(dt=sc.dt, max_iters=sc.iters,
-                        coupling=ovl.COUPLING_PREV_IMPULSE if coupled else ovl.COUPLING_NONE)
+                        coupling=coupled)
     w = ovl.World(sc, p)
     w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
     # three plain-start oracle steps make the state and cache the learned step starts from
@@ -91,9 +93,9 @@ def test_learned_step_matches_oracle(which, coupled):
     fe = np.abs(feat[kinds == 1] - o["copy_feat"][kinds == 1]).max()
     sc_ = np.maximum(1.0, np.abs(o["copy_lambdal"]).max())
     le = np.abs(laml - o["copy_lambdal"]).max() / sc_
-    if coupled:
+    if coupled == ovl.COUPLING_PREV_IMPULSE:
         assert np.abs(o["rep_cpl"]).max() > 0.0
-    log(f"  {which}{' coupled' if coupled else ''}: features max err {fe:.2e}, learned start max rel err {le:.2e}, guard gpu {guard} "
+    log(f"  {which} coupling {coupled}: features max err {fe:.2e}, learned start max rel err {le:.2e}, guard gpu {guard} "
         f"oracle {o['part_guard']}, rho0 gpu {rho0.tolist()} oracle {o['part_rho0'].tolist()}")
     assert fe < 1e-4
     assert le < 2e-2
