@@ -163,6 +163,7 @@ struct WP {
   float4* rep_ax;               // [Rcap] capsule axis u and 1/I_axis - 1/I_perp of each replica
   float4* rep_cpl;              // [2*Rcap] interface-coupling impulse per replica: (dv, 0), then (dw, 0)
   float* rep_isc;               // [Rcap] mass splitting: inverse mass and inertia factor 1/w per replica
+  float2* rep_im;               // [Rcap] inverse mass and inverse inertia of each replica (with that factor)
   float4* r_lam;                // [Mcap] impulses (3 used)
   float4* r_lam0;               // [Mcap] warm-start impulses
   float4* rep_v4;               // [2*Rcap] velocity storage of partitions too large for LDS

@@ -1060,9 +1060,9 @@ __device__ void load_replicas(const WP& w, Vel V, int r0, int nr) {
   const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
   for (int r = threadIdx.x; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
-    const float sp = w.msplit ? w.rep_isc[r0 + r] : 1.0f;
-    float4 lin = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, w.b_invm[b] * sp);
-    float4 ang = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], w.b_invI[b] * sp);
+    const float2 im = w.rep_im[r0 + r];
+    float4 lin = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, im.x);
+    float4 ang = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], im.y);
     if (w.couple) {
       const float4 cv = w.rep_cpl[r0 + r], cw = w.rep_cpl[w.Rcap + r0 + r];
       lin.x += cv.x;
@@ -1356,22 +1356,26 @@ __global__ __launch_bounds__(kOrderBS) void k_part_order(WP w) {
   }
 }
 
-// Mass splitting: every replica of an overlap body carries the share w of the
-// body that the blend will give it; its inverse mass and inertia are divided
-// by w (a replica of weight 0 keeps the whole body).
-__global__ void k_mass_split(WP w) {
+// Inverse mass and inverse inertia of every replica, partition-major, for the
+// sweeps.  With mass splitting a replica of an overlap body carries the share
+// w of the body that the blend will give it: both are divided by w (a replica
+// of weight 0 keeps the whole body), and the factor 1/w is kept for the rows.
+__global__ void k_rep_mass(WP w) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= w.N || step_failed(w)) return;
   const int n = __popcll(w.mask[v]);
   const int bm0 = w.rep_off_bm[v];
-  if (n == 1) {
-    w.rep_isc[w.rep_pm_of_bm[bm0]] = 1.0f;
-    return;
-  }
-  const float sum = inv_dist_sum(w, bm0, n);
+  const float im = w.b_invm[v], ii = w.b_invI[v];
+  const float sum = w.msplit && n > 1 ? inv_dist_sum(w, bm0, n) : 0.0f;
   for (int k = 0; k < n; ++k) {
-    const float wt = blend_weight(w, w.rep_D_bm[bm0 + k], sum, n);
-    w.rep_isc[w.rep_pm_of_bm[bm0 + k]] = wt > 0.0f ? 1.0f / wt : 1.0f;
+    float s = 1.0f;
+    if (w.msplit && n > 1) {
+      const float wt = blend_weight(w, w.rep_D_bm[bm0 + k], sum, n);
+      s = wt > 0.0f ? 1.0f / wt : 1.0f;
+    }
+    const int r = w.rep_pm_of_bm[bm0 + k];
+    if (w.msplit) w.rep_isc[r] = s;
+    w.rep_im[r] = make_float2(im * s, ii * s);
   }
 }
 
@@ -1802,8 +1806,8 @@ hipError_t launch_solve_pre(const WP& w, hipStream_t s) {
     k_couple<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
-  if (w.msplit && w.N > 0) {
-    k_mass_split<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
+  if (w.N > 0) {
+    k_rep_mass<<<nblocks(w.N, kBlock), kBlock, 0, s>>>(w);
     if ((e = hipGetLastError())) return e;
   }
   if (w.G > 0) {

@@ -160,7 +160,6 @@ struct ovl_world {
     w.r_gen = alloc<float4>(g, w.has_caps ? (size_t)2 * Mcap : 1, ok);
     w.rep_ax = alloc<float4>(g, w.has_caps ? (size_t)Rcap : 1, ok);
     w.rep_cpl = alloc<float4>(g, (size_t)2 * Rcap, ok);
-    w.rep_isc = alloc<float>(g, Rcap, ok);
     w.r_ids = alloc<int2>(g, Mcap, ok);
     w.r_lam = alloc<float4>(g, Mcap, ok);
     w.r_lam0 = alloc<float4>(g, Mcap, ok);
@@ -173,6 +172,8 @@ struct ovl_world {
     w.wc_val = alloc<float>(g, (size_t)4 * Mcap, ok);
     w.wc_k64 = alloc<uint64_t>(g, Mcap, ok);
     w.mc_blk[2] = alloc<int32_t>(g, (size_t)(nblocks(Ccap, 256) + 1) * 64, ok);
+    w.rep_isc = alloc<float>(g, Rcap, ok);
+    w.rep_im = alloc<float2>(g, Rcap, ok);
     return ok;
   }
 
