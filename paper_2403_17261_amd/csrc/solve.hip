@@ -1053,14 +1053,18 @@ __device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, i
 
 // replica velocities with gravity applied (v~ = v + h g), plus the interface
 // coupling impulse when that option is on, and inverse masses (the replica's
-// share of them under mass splitting)
-template <int BS>
+// share of them under mass splitting, kSplit)
+template <int BS, bool kSplit>
 __device__ void load_replicas(const WP& w, Vel V, int r0, int nr) {
   const int N = w.N;
   const float hgx = w.dt * w.gx, hgy = w.dt * w.gy, hgz = w.dt * w.gz;
   for (int r = threadIdx.x; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
-    const float2 im = w.rep_im[r0 + r];
+    float2 im;
+    if constexpr (kSplit)
+      im = w.rep_im[r0 + r];
+    else
+      im = make_float2(w.b_invm[b], w.b_invI[b]);
     float4 lin = make_float4(w.st[7 * N + b] + hgx, w.st[8 * N + b] + hgy, w.st[9 * N + b] + hgz, im.x);
     float4 ang = make_float4(w.st[10 * N + b], w.st[11 * N + b], w.st[12 * N + b], im.y);
     if (w.couple) {
@@ -1131,7 +1135,7 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
 // Initial residual of a start (plain, or learned for contacts): apply it in
 // solve order, take the largest natural-map residual of the partition's rows,
 // then restore v~.  Uniform over the workgroup.
-template <int BS, bool kCaps>
+template <int BS, bool kCaps, bool kSplit>
 __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int* coff, int r0, int nr,
                                 bool learned, float* red) {
   const int tid = threadIdx.x;
@@ -1158,14 +1162,14 @@ __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int*
     e = fmaxf(e, copy_residual(R, A, B, w.cfm));
   }
   e = block_max<BS>(e, red);
-  load_replicas<BS>(w, V, r0, nr);
+  load_replicas<BS, kSplit>(w, V, r0, nr);
   __syncthreads();
   return e;
 }
 
 // Solve one partition with a workgroup of BS threads.  V holds its replica
 // velocities (LDS, or its slice of rep_v4 for the global variant).
-template <int BS, bool kCaps>
+template <int BS, bool kCaps, bool kSplit>
 __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red) {
   const int tid = threadIdx.x;
   const int N = w.N;
@@ -1175,13 +1179,13 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   const int ncol = w.part_ncol[p];
   const bool packed = nr < kPackReps;  // uniform: ids from the impulses' fourth component
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
-  load_replicas<BS>(w, V, r0, nr);
+  load_replicas<BS, kSplit>(w, V, r0, nr);
   __syncthreads();
   float rl = 0.0f;
   if (w.learned) {
     // keep the learned start only when its initial residual is below the plain start's
-    const float rho_p = start_residual<BS, kCaps>(w, V, s0, ncol, coff, r0, nr, false, red);
-    const float rho_l = start_residual<BS, kCaps>(w, V, s0, ncol, coff, r0, nr, true, red);
+    const float rho_p = start_residual<BS, kCaps, kSplit>(w, V, s0, ncol, coff, r0, nr, false, red);
+    const float rho_l = start_residual<BS, kCaps, kSplit>(w, V, s0, ncol, coff, r0, nr, true, red);
     bool use = rho_l < rho_p;
     if (w.force_guard && w.part_force_guard[p] >= 0) use = w.part_force_guard[p] != 0;
     if (use)
@@ -1292,7 +1296,7 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
 // otherwise velocities in global memory, for the larger ones.  Either one
 // workgroup per partition, or (w.pgs_persistent) a grid of resident
 // workgroups that take partitions from an atomic queue until it is empty.
-template <int BS, int kReps, bool kLds, bool kCaps>
+template <int BS, int kReps, bool kLds, bool kCaps, bool kSplit>
 __global__ __launch_bounds__(BS) void k_pgs(WP w) {
   extern __shared__ float4 sm4[];
   __shared__ int coff[kColStride];
@@ -1322,7 +1326,7 @@ __global__ __launch_bounds__(BS) void k_pgs(WP w) {
     const int nr = w.part_rep_off[p + 1] - w.part_rep_off[p];
     if (kLds == (nr <= kReps)) {  // otherwise the other variant handles this partition
       const Vel V = kLds ? Vel{sm4, kReps} : Vel{w.rep_v4 + w.part_rep_off[p], w.Rcap};
-      solve_partition<BS, kCaps>(w, p, V, coff, red);
+      solve_partition<BS, kCaps, kSplit>(w, p, V, coff, red);
     }
     if (!w.pgs_persistent) break;
   }
@@ -1649,10 +1653,11 @@ template <int BS, int R>
 hipError_t set_attrs_t() {
   hipError_t e = hipSuccess;
   const int lds = 2 * R * (int)sizeof(float4);
-  if ((e = hipFuncSetAttribute((const void*)k_pgs<BS, R, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds)))
-    return e;
-  return hipFuncSetAttribute((const void*)k_pgs<BS, R, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const void* fns[4] = {(const void*)k_pgs<BS, R, true, false, false>, (const void*)k_pgs<BS, R, true, true, false>,
+                        (const void*)k_pgs<BS, R, true, false, true>, (const void*)k_pgs<BS, R, true, true, true>};
+  for (const void* f : fns)
+    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds))) return e;
+  return e;
 }
 
 template <int BS, int R>
@@ -1660,11 +1665,13 @@ hipError_t occupancy_t(bool caps, int* per_cu_lds, int* per_cu_glob) {
   const size_t lds = 2 * (size_t)R * sizeof(float4);
   hipError_t e;
   if (caps) {
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, true>, BS, lds))) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, true>, BS, 0);
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, true, false>, BS, lds)))
+      return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, true, false>, BS, 0);
   }
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, false>, BS, lds))) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, false>, BS, 0);
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, false, false>, BS, lds)))
+    return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, false, false>, BS, 0);
 }
 
 template <int BS, int R>
@@ -1674,14 +1681,24 @@ hipError_t launch_pgs_t(const WP& w, hipStream_t s) {
   const int g1 = w.pgs_persistent ? std::min(w.G, w.pgs_grid[1]) : w.G;
   hipError_t e;
   if (w.pgs_persistent && (e = fill_i32(w.pgs_queue, 0, 2, s))) return e;
-  if (w.has_caps) {
-    k_pgs<BS, R, true, true><<<g0, BS, lds, s>>>(w);
+  // mass splitting reads the replicas' inverse masses from their own array
+  // (a variant of its own, so the default sweeps keep their per-body loads)
+  if (w.has_caps && w.msplit) {
+    k_pgs<BS, R, true, true, true><<<g0, BS, lds, s>>>(w);
     if ((e = hipGetLastError())) return e;
-    k_pgs<BS, R, false, true><<<g1, BS, 0, s>>>(w);
+    k_pgs<BS, R, false, true, true><<<g1, BS, 0, s>>>(w);
+  } else if (w.has_caps) {
+    k_pgs<BS, R, true, true, false><<<g0, BS, lds, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+    k_pgs<BS, R, false, true, false><<<g1, BS, 0, s>>>(w);
+  } else if (w.msplit) {
+    k_pgs<BS, R, true, false, true><<<g0, BS, lds, s>>>(w);
+    if ((e = hipGetLastError())) return e;
+    k_pgs<BS, R, false, false, true><<<g1, BS, 0, s>>>(w);
   } else {
-    k_pgs<BS, R, true, false><<<g0, BS, lds, s>>>(w);
+    k_pgs<BS, R, true, false, false><<<g0, BS, lds, s>>>(w);
     if ((e = hipGetLastError())) return e;
-    k_pgs<BS, R, false, false><<<g1, BS, 0, s>>>(w);
+    k_pgs<BS, R, false, false, false><<<g1, BS, 0, s>>>(w);
   }
   return hipGetLastError();
 }
