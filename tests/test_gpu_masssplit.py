@@ -7,7 +7,8 @@ parity test does: jointed chains with displaced links (ball-joint rows with
 scaled inverse masses and inertias), a sphere lattice on the ground with one-
 and two-hop halos (contacts with friction), a squeezed pile of capsules (the
 scaled inverse inertia tensor), dynamically balanced worker sets, and two
-scenes in one world.
+scenes in one world.  Every launch configuration gives the same bits, the
+global-memory variant of the split sweeps included.
 
 At the size of the 100k tower (no ground, no gravity, random velocities, a
 geodesic search deep enough that every replica has a weight) one step
@@ -148,3 +149,27 @@ def test_tower_conserves_momentum_at_full_size():
     # the momentum scale; without splitting the blend loses 1e-4 of it
     assert err[ovl.COUPLING_MASS_SPLIT] < 1e-7
     assert err[ovl.COUPLING_NONE] > 100 * 1e-7
+
+
+def test_every_launch_configuration_gives_the_same_bits():
+    # chains in four slabs: partitions above the 1200- and 2400-replica LDS
+    # tiles, so the global-memory variant of the split sweeps takes part
+    sc = scenes.config3(0, n_chains=64, links=200)
+    owner = (sc.owner // 4).astype(np.int32)
+    pps = np.array([4], np.int32)
+    ref = None
+    for c in ovl.launch_candidates():
+        for graph in (0, 1):
+            p = ovl.make_params(dt=sc.dt, max_iters=sc.iters, coupling=ovl.COUPLING_MASS_SPLIT)
+            w = ovl.World(sc, p)
+            w.set_partitions(owner, pps, halo_k=3, beta=sc.beta)
+            w.set_launch(**dict(c, graph=graph))
+            w.step(20)
+            st = w.read_state()
+            if ref is None:
+                ref = st
+                big = int(np.diff(w.debug("part_rep_off").astype(np.int64)).max())
+                log(f"  {sc.n_bodies} bodies in 4 partitions, largest {big} replicas")
+                assert big > 2400
+            assert np.array_equal(st, ref), (c, graph)
+            w.close()
