@@ -65,7 +65,7 @@ class _Params(C.Structure):
                 ("brute_force_contacts", C.c_int32), ("seed", C.c_uint32), ("learned", C.c_int32),
                 ("mlp", C.c_void_p), ("forced_guard", C.c_void_p), ("lb_masks", C.c_void_p),
                 ("lb_depth", C.c_int32), ("equal_weights", C.c_int32),
-                ("coupling", C.c_int32)]
+                ("coupling", C.c_int32), ("threads", C.c_int32)]
 
 
 class _Cache(C.Structure):
@@ -74,10 +74,11 @@ class _Cache(C.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FP contraction)."""
+    """Compile the oracle with gcc (no fast-math, no FP contraction; OpenMP for the optional
+    one-thread-per-partition solves)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                                "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -156,7 +157,7 @@ def mlp_infer(params, x12):
 DEFAULTS = dict(dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), cfm=0.0, erp=0.2, max_iters=20, tol=1e-4,
                 adaptive=False, warmstart=True, halo_k=1, beta=4, seed=0, brute_force=False, mlp=None,
                 forced_guard=None, lb_masks=None, lb_depth=0, equal_weights=False,
-                coupling=False)
+                coupling=False, threads=1)
 
 
 def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced_iters=None, **kw):
@@ -201,6 +202,7 @@ def step(scene, state=None, owner=None, parts_per_scene=None, cache=None, forced
         pr.forced_guard = _ptr(arr(p["forced_guard"], np.int32))
     pr.equal_weights = int(bool(p["equal_weights"]))
     pr.coupling = int(p["coupling"])  # 0 none, 1 previous-step impulses, 2 mass splitting
+    pr.threads = max(1, int(p["threads"]))  # partitions solved on this many threads (same bits)
     if pr.coupling not in (0, 1, 2):
         raise ValueError("coupling must be 0, 1 or 2")
     if p["lb_masks"] is not None:

@@ -1508,6 +1508,10 @@ orc_result* orc_step(const orc_scene* sc, const float* state, const int32_t* own
   int32_t* piters = (int32_t*)xalloc((size_t)(G ? G : 1) * 4);
   double* presid = (double*)xalloc((size_t)(G ? G : 1) * 8);
   int unconverged = 0;
+  /* The partitions share no replica and no copy: each is solved on its own,
+   * like the paper's workers, on up to prm->threads threads. */
+  const int nthreads = prm->threads > 1 ? prm->threads : 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(+ : unconverged) if (nthreads > 1)
   for (int32_t p = 0; p < G; ++p) {
     int64_t m0 = pcop[p], m1 = pcop[p + 1], nm = m1 - m0;
     replica* rp = rep + prep[p];

@@ -72,6 +72,11 @@ typedef struct {
    * blend sum_i w_i v_i equals the body's free velocity plus the sum of the
    * partitions' impulses applied to the whole body. */
   int32_t coupling;
+  /* Threads for the projected Gauss-Seidel solves (1: sequential).  The
+   * partitions are independent sub-solves (section 4: one worker each), so
+   * solving them on several threads, one partition per thread at a time,
+   * gives the same bits as the sequential loop. */
+  int32_t threads;
 } orc_params;
 
 #define ORC_MLP_IN 12

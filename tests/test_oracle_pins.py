@@ -642,3 +642,14 @@ def test_learned_start_guard_and_features(orc):
     bad[-3] = 5.0                      # five times too large: the plain (zero) start wins
     o3 = orc.step(sc, warmstart=False, mlp=bad, adaptive=True, tol=1e-9, max_iters=50)
     assert o3["part_guard"][0] == 0
+
+
+def test_partition_threads_give_the_same_bits(orc):
+    """The partitions are independent sub-solves: solving them on several threads
+    (the worker-per-core CPU baseline) changes no bit of the step."""
+    sc = scenes.config1(1)
+    ref = orc.step(sc, adaptive=True, tol=1e-6, max_iters=500)
+    for th in (2, 3):
+        o = orc.step(sc, adaptive=True, tol=1e-6, max_iters=500, threads=th)
+        for k in ("state", "copy_lambda", "part_iters", "part_resid", "rep_state"):
+            assert np.array_equal(o[k], ref[k]), (th, k)
