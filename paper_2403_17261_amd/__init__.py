@@ -80,7 +80,7 @@ class ovl_step_stats(C.Structure):
 class ovl_counters(C.Structure):
     _fields_ = [("steps", C.c_int64), ("sweeps_max_total", C.c_int64), ("sweeps_part_total", C.c_int64),
                 ("unconverged_total", C.c_int64), ("pgs_bytes", C.c_int64), ("pgs_launches", C.c_int64),
-                ("pgs_ms", C.c_double), ("steps_capped", C.c_int64)]
+                ("pgs_ms", C.c_double), ("steps_capped", C.c_int64), ("pgs_ops", C.c_int64)]
 
 
 class ovl_launch_cfg(C.Structure):

@@ -30,6 +30,10 @@ namespace ovl {
 
 namespace {
 
+// Spatial hash of a grid cell: the three large primes of Teschner et al.,
+// "Optimized Spatial Hashing for Collision Detection of Deformable Objects"
+// (VMV 2003), XOR-combined; the scene index is mixed in with Knuth's
+// multiplicative constant 2654435761 (TAOCP vol. 3, section 6.4).
 __device__ __forceinline__ uint32_t cell_hash(int s, int x, int y, int z) {
   return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u) ^
          ((uint32_t)s * 2654435761u);

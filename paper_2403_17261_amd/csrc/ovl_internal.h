@@ -201,7 +201,8 @@ struct WP {
   float* stat_f;                // [4]: exact residual
   int64_t* stat_i64;            // [8]: 0 sum over steps of the largest sweep count, 1 unconverged partitions,
                                 //      2 algorithmic bytes of the sweeps, 3 sweeps summed over partitions,
-                                //      4 committed steps
+                                //      4 committed steps, 5 steps with a capped partition, 6 algorithmic
+                                //      FP32 operations of the sweeps
   // dynamic load balancing: worker sets carried from step to step
   int32_t lb_on;                // 1: sets carried and updated from each step's contacts; 0: k-hop halo
   int32_t lb_depth;             // growth depth of the inter-worker rule
@@ -248,6 +249,15 @@ hipError_t launch_digest(const WP& w, unsigned long long* out, hipStream_t s);
 constexpr int64_t kBytesDynDyn = 220;
 constexpr int64_t kBytesStatic = 164;
 constexpr int64_t kBytesJoint = 192;
+// Algorithmic FP32 operations of one sweep per constraint copy (each add,
+// multiply, fused multiply-add, min and max counted once; the row formulas of
+// the sweep): a sphere contact rebuilds its tangents (11), forms the relative
+// velocity terms and the three projected updates (n, t1, t2) and applies the
+// impulse to both bodies (88); with a static body the second body's terms drop
+// out (74); a ball joint solves its three axis rows in turn (63).
+constexpr int64_t kOpsDynDyn = 88;
+constexpr int64_t kOpsStatic = 74;
+constexpr int64_t kOpsJoint = 63;
 hipError_t pgs_set_attributes();
 // dynamic load balancing (between the graph and the replica table; commit after the blend)
 hipError_t launch_balance(const WP& w, hipStream_t s);

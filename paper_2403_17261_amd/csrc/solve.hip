@@ -35,6 +35,12 @@
 #include <algorithm>
 #include "wave.h"
 
+// No implicit fused multiply-add in this file: every fused operation is written
+// out with fmaf.  The sweeps are compiled in several variants (velocities in LDS
+// or in global memory, block sizes); with the fusions fixed in the source every
+// variant rounds the same way, so every launch configuration gives the same bits.
+#pragma clang fp contract(off)
+
 namespace ovl {
 
 namespace {
@@ -43,13 +49,18 @@ struct f3 {
   float x, y, z;
 };
 __device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; }
-__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)); }
 __device__ __forceinline__ f3 cross(f3 a, f3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+  return {fmaf(a.y, b.z, -(a.z * b.y)), fmaf(a.z, b.x, -(a.x * b.z)), fmaf(a.x, b.y, -(a.y * b.x))};
 }
 __device__ __forceinline__ f3 add(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ f3 sub(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ f3 scale(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+// c + a s and c - a s, fused per component
+__device__ __forceinline__ f3 madd(f3 c, f3 a, float s) { return {fmaf(a.x, s, c.x), fmaf(a.y, s, c.y), fmaf(a.z, s, c.z)}; }
+__device__ __forceinline__ f3 msub(f3 c, f3 a, float s) {
+  return {fmaf(-a.x, s, c.x), fmaf(-a.y, s, c.y), fmaf(-a.z, s, c.z)};
+}
 
 __device__ __forceinline__ bool step_failed(const WP& w) {
   return __hip_atomic_load(&w.scal[SC_FLAGS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -62,8 +73,9 @@ __device__ __forceinline__ bool step_failed(const WP& w) {
 __device__ __forceinline__ void tangents_from(f3 n, float a, f3& t1, f3& t2) {
   const float s = copysignf(1.0f, n.z);
   const float b = n.x * n.y * a;
-  t1 = mk(1.0f + s * n.x * n.x * a, s * b, -s * n.x);
-  t2 = mk(b, s + n.y * n.y * a, -n.y);
+  const float sx = s * n.x;
+  t1 = mk(fmaf(sx * n.x, a, 1.0f), s * b, -sx);
+  t2 = mk(b, fmaf(n.y * n.y, a, s), -n.y);
 }
 
 __device__ __forceinline__ float tangents(f3 n, f3& t1, f3& t2) {
@@ -93,7 +105,7 @@ __device__ __forceinline__ f3 body_axis(const WP& w, int b) {
 // world inverse inertia of an axisymmetric body applied to x:
 // I^-1 x = x / I_perp + (1/I_axis - 1/I_perp) (u.x) u
 __device__ __forceinline__ f3 inv_inertia(float ii, f3 u, float dI, f3 x) {
-  return add(scale(x, ii), scale(u, dI * dot(u, x)));
+  return madd(scale(x, ii), u, dI * dot(u, x));
 }
 
 // Blend weight (Eq. 15-16) of a replica at geodesic distance D of a body in
@@ -841,6 +853,45 @@ __device__ __forceinline__ void load_rec(const WP& w, int slot, Rec& R, bool pac
   decode<kCaps>(R, packed);
 }
 
+// The record arrays of one partition, from its first slot: the sweeps address
+// a slot by its 32-bit byte offset from these scalar bases (one vector
+// instruction per slot for all of its loads and its impulse store).
+struct Slots {
+  const char *r0, *r1, *r2, *ids, *g0, *g1;
+  char* lam;
+};
+
+__device__ __forceinline__ Slots slots_of(const WP& w, int s0) {
+  // s0 is the same in every lane; taking it from the first lane keeps the
+  // bases in scalar registers
+  const int64_t u = __builtin_amdgcn_readfirstlane(s0);
+  const int64_t MC = w.Mcap;
+  Slots S;
+  S.r0 = reinterpret_cast<const char*>(w.r_rec + u);
+  S.r1 = reinterpret_cast<const char*>(w.r_rec + MC + u);
+  S.r2 = reinterpret_cast<const char*>(w.r_rec + 2 * MC + u);
+  S.ids = reinterpret_cast<const char*>(w.r_ids + u);
+  S.g0 = reinterpret_cast<const char*>(w.r_gen + u);
+  S.g1 = reinterpret_cast<const char*>(w.r_gen + MC + u);
+  S.lam = reinterpret_cast<char*>(w.r_lam + u);
+  return S;
+}
+
+// fetch_rec for the slot at local index l of the partition (see fetch_rec)
+template <bool kCaps>
+__device__ __forceinline__ void fetch_local(const Slots& S, uint32_t l, Rec& R, bool packed) {
+  const uint32_t o = l << 4;
+  R.r0 = *reinterpret_cast<const float4*>(S.r0 + o);
+  R.r1 = *reinterpret_cast<const float4*>(S.r1 + o);
+  R.r2 = *reinterpret_cast<const float4*>(S.r2 + o);
+  if (!packed) R.id = *reinterpret_cast<const int2*>(S.ids + (l << 3));
+  R.lam = *reinterpret_cast<const float4*>(S.lam + o);
+  if (kCaps) {
+    R.g0 = *reinterpret_cast<const float4*>(S.g0 + o);
+    R.g1 = *reinterpret_cast<const float4*>(S.g1 + o);
+  }
+}
+
 struct Bod {
   f3 v, w;
   float im, ii;
@@ -885,20 +936,20 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
   float d0, d1, d2;
   if (solve) {
     const f3 dv = sub(B.v, A.v);
-    const f3 sw = add(scale(A.w, la), scale(B.w, lb));
+    const f3 sw = madd(scale(B.w, lb), A.w, la);
     // normal
-    const float un = dot(n, dv) + bias + cfm * lam.x;
-    const float ln = fmaxf(lam.x - un * R.r2.x, 0.0f);
+    const float un = fmaf(cfm, lam.x, dot(n, dv) + bias);
+    const float ln = fmaxf(fmaf(-un, R.r2.x, lam.x), 0.0f);
     d0 = ln - lam.x;
     lam.x = ln;
     // friction box of the new normal impulse
     const float hi = mu * ln;
-    const float u1 = dot(t1, dv) - dot(t2, sw) + cfm * lam.y;
-    const float l1 = fminf(fmaxf(lam.y - u1 * R.r2.y, -hi), hi);
+    const float u1 = fmaf(cfm, lam.y, dot(t1, dv) - dot(t2, sw));
+    const float l1 = fminf(fmaxf(fmaf(-u1, R.r2.y, lam.y), -hi), hi);
     d1 = l1 - lam.y;
     lam.y = l1;
-    const float u2 = dot(t2, dv) + dot(t1, sw) + cfm * lam.z;
-    const float l2 = fminf(fmaxf(lam.z - u2 * R.r2.y, -hi), hi);
+    const float u2 = fmaf(cfm, lam.z, dot(t2, dv) + dot(t1, sw));
+    const float l2 = fminf(fmaxf(fmaf(-u2, R.r2.y, lam.z), -hi), hi);
     d2 = l2 - lam.z;
     lam.z = l2;
     rl = fmaxf(rl, fmaxf(fabsf(d0) * R.r2.z, fmaxf(fabsf(d1), fabsf(d2)) * R.r2.w));
@@ -907,12 +958,12 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
     d1 = lam.y;
     d2 = lam.z;
   }
-  const f3 P = add(add(scale(n, d0), scale(t1, d1)), scale(t2, d2));
-  const f3 Q = sub(scale(t2, d1), scale(t1, d2));
-  A.v = sub(A.v, scale(P, A.im));
-  B.v = add(B.v, scale(P, B.im));
-  A.w = sub(A.w, scale(Q, A.ii * la));
-  B.w = sub(B.w, scale(Q, B.ii * lb));
+  const f3 P = madd(madd(scale(n, d0), t1, d1), t2, d2);
+  const f3 Q = msub(scale(t2, d1), t1, d2);
+  A.v = msub(A.v, P, A.im);
+  B.v = madd(B.v, P, B.im);
+  A.w = msub(A.w, Q, A.ii * la);
+  B.w = msub(B.w, Q, B.ii * lb);
 }
 
 // Ball joint, rows along -e_k: J_k v = (v_a + w_a x r_a - v_b - w_b x r_b)_k;
@@ -924,13 +975,14 @@ __device__ __forceinline__ f3 cross_axis(f3 r, int k) {
   return k == 0 ? mk(0.0f, r.z, -r.y) : (k == 1 ? mk(-r.z, 0.0f, r.x) : mk(r.y, -r.x, 0.0f));
 }
 
-__device__ __forceinline__ void add_axis(f3& v, int k, float s) {
+// v_k += a b (fused)
+__device__ __forceinline__ void add_axis(f3& v, int k, float a, float b) {
   if (k == 0)
-    v.x += s;
+    v.x = fmaf(a, b, v.x);
   else if (k == 1)
-    v.y += s;
+    v.y = fmaf(a, b, v.y);
   else
-    v.z += s;
+    v.z = fmaf(a, b, v.z);
 }
 
 template <bool solve, bool kGen = false>
@@ -948,38 +1000,38 @@ __device__ __forceinline__ void joint_rows(const Rec& R, Bod& A, Bod& B, float c
       const f3 ca = cross(A.w, ra), cb = cross(B.w, rb);
       const float vr = k == 0 ? (A.v.x + ca.x) - (B.v.x + cb.x)
                               : (k == 1 ? (A.v.y + ca.y) - (B.v.y + cb.y) : (A.v.z + ca.z) - (B.v.z + cb.z));
-      const float wv = vr + bias[k] + cfm * l[k];
-      const float nl = l[k] - wv * invd[k];
+      const float wv = fmaf(cfm, l[k], vr + bias[k]);
+      const float nl = fmaf(-wv, invd[k], l[k]);
       dl = nl - l[k];
       l[k] = nl;
       rl = fmaxf(rl, fabsf(dl) * rcp_fast(invd[k]));
     } else {
       dl = l[k];
     }
-    add_axis(A.v, k, A.im * dl);
-    add_axis(B.v, k, -B.im * dl);
+    add_axis(A.v, k, A.im, dl);
+    add_axis(B.v, k, -B.im, dl);
     const f3 xa = cross_axis(ra, k), xb = cross_axis(rb, k);
     if (kGen) {
-      A.w = add(A.w, scale(inv_inertia(A.ii, mk(axA.x, axA.y, axA.z), axA.w, xa), dl));
-      B.w = sub(B.w, scale(inv_inertia(B.ii, mk(axB.x, axB.y, axB.z), axB.w, xb), dl));
+      A.w = madd(A.w, inv_inertia(A.ii, mk(axA.x, axA.y, axA.z), axA.w, xa), dl);
+      B.w = msub(B.w, inv_inertia(B.ii, mk(axB.x, axB.y, axB.z), axB.w, xb), dl);
     } else {
       const float sa = A.ii * dl, sb = B.ii * dl;
       // only the two nonzero components of r x e_k
       if (k == 0) {
-        A.w.y += sa * xa.y;
-        A.w.z += sa * xa.z;
-        B.w.y -= sb * xb.y;
-        B.w.z -= sb * xb.z;
+        A.w.y = fmaf(sa, xa.y, A.w.y);
+        A.w.z = fmaf(sa, xa.z, A.w.z);
+        B.w.y = fmaf(-sb, xb.y, B.w.y);
+        B.w.z = fmaf(-sb, xb.z, B.w.z);
       } else if (k == 1) {
-        A.w.x += sa * xa.x;
-        A.w.z += sa * xa.z;
-        B.w.x -= sb * xb.x;
-        B.w.z -= sb * xb.z;
+        A.w.x = fmaf(sa, xa.x, A.w.x);
+        A.w.z = fmaf(sa, xa.z, A.w.z);
+        B.w.x = fmaf(-sb, xb.x, B.w.x);
+        B.w.z = fmaf(-sb, xb.z, B.w.z);
       } else {
-        A.w.x += sa * xa.x;
-        A.w.y += sa * xa.y;
-        B.w.x -= sb * xb.x;
-        B.w.y -= sb * xb.y;
+        A.w.x = fmaf(sa, xa.x, A.w.x);
+        A.w.y = fmaf(sa, xa.y, A.w.y);
+        B.w.x = fmaf(-sb, xb.x, B.w.x);
+        B.w.y = fmaf(-sb, xb.y, B.w.y);
       }
     }
   }
@@ -1008,32 +1060,50 @@ __device__ __forceinline__ void gen_contact_rows(const Rec& R, Bod& A, Bod& B, f
     float dl;
     if (solve) {
       const float vr = dot(d, sub(B.v, A.v)) + dot(cb, B.w) - dot(ca, A.w);
-      const float wv = vr + (k == 0 ? bias : 0.0f) + cfm * l[k];
+      const float wv = fmaf(cfm, l[k], vr + (k == 0 ? bias : 0.0f));
       const float hi = k == 0 ? INFINITY : mu * l[0];
       const float lo = k == 0 ? 0.0f : -hi;
-      const float nl = fminf(fmaxf(l[k] - wv * invd[k], lo), hi);
+      const float nl = fminf(fmaxf(fmaf(-wv, invd[k], l[k]), lo), hi);
       dl = nl - l[k];
       l[k] = nl;
       rl = fmaxf(rl, fabsf(dl) * Arr[k]);
     } else {
       dl = l[k];
     }
-    A.v = sub(A.v, scale(d, A.im * dl));
-    B.v = add(B.v, scale(d, B.im * dl));
-    A.w = sub(A.w, scale(inv_inertia(A.ii, ua, axA.w, ca), dl));
-    B.w = add(B.w, scale(inv_inertia(B.ii, ub, axB.w, cb), dl));
+    A.v = msub(A.v, d, A.im * dl);
+    B.v = madd(B.v, d, B.im * dl);
+    A.w = msub(A.w, inv_inertia(A.ii, ua, axA.w, ca), dl);
+    B.w = madd(B.w, inv_inertia(B.ii, ub, axB.w, cb), dl);
   }
 }
 
-template <bool solve, bool kCaps = false>
-__device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, int slot, int r0 = 0) {
+// A static second body in the sweeps of partitions held in global memory: a
+// zero velocity and zero inverse mass and inertia, never written.
+__device__ float4 g_zero_body[2];
+
+// One copy: gather its bodies, solve (or, with solve false, apply) its rows,
+// scatter the velocities, store the impulses at lam_out.  kSweep: the second
+// body is always loaded, a static one as a zero body: at index -1 of V when
+// the velocities are in LDS (kLds), from g_zero_body otherwise, so that the
+// arithmetic is the same in both and no lane branches on it before the store.
+// A zero body stays zero in LDS because a zero inverse mass adds only zeros.
+template <bool solve, bool kCaps = false, bool kSweep = false, bool kLds = false>
+__device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, float4* lam_out, int r0 = 0) {
   Bod A = ld_body(V, R.ia);
   Bod B;
   const bool hasB = R.ib >= 0;
-  if (hasB)
+  if (kSweep && kLds) {
     B = ld_body(V, R.ib);
-  else
+  } else if (kSweep) {
+    const float4* zl = hasB ? V.p + R.ib : g_zero_body;
+    const float4* za = hasB ? V.p + R.ib + V.stride : g_zero_body + 1;
+    const float4 a = *zl, b = *za;
+    B = {mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), a.w, b.w};
+  } else if (hasB) {
+    B = ld_body(V, R.ib);
+  } else {
     B = {mk(0, 0, 0), mk(0, 0, 0), 0.0f, 0.0f};
+  }
   if (kCaps && R.gen) {
     const float4 axA = w.rep_ax[r0 + R.ia];
     const float4 axB = hasB ? w.rep_ax[r0 + R.ib] : float4{};
@@ -1047,8 +1117,22 @@ __device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, i
     contact_rows<solve>(R, A, B, w.cfm, R.lam, rl);
   }
   st_body(V, R.ia, A);
-  if (hasB) st_body(V, R.ib, B);
-  if (solve) w.r_lam[slot] = R.lam;
+  if ((kSweep && kLds) || hasB) st_body(V, R.ib, B);
+  if (solve) *lam_out = R.lam;
+}
+
+// s_waitcnt operand (gfx9 encoding) that waits for every vector-memory access
+// of the wave to complete and leaves the other counters free.
+constexpr int kWaitVmem0 = 0x0F70;
+
+// Workgroup barrier after which other waves read replica velocities this wave
+// wrote.  In LDS the barrier's wait for the wave's LDS operations orders them.
+// In global memory (partitions above the LDS tile) the workgroup barrier does
+// not wait for the wave's stores, so the wave waits for them first.
+template <bool kLds>
+__device__ __forceinline__ void vel_sync() {
+  if (!kLds) __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+  __syncthreads();
 }
 
 // replica velocities with gravity applied (v~ = v + h g), plus the interface
@@ -1109,7 +1193,7 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
       vr[1] = dot(t1, dv) + dot(cross(rb, t1), B.w) - dot(cross(ra, t1), A.w);
       vr[2] = dot(t2, dv) + dot(cross(rb, t2), B.w) - dot(cross(ra, t2), A.w);
     } else {
-      const f3 sw = add(scale(A.w, R.r1.x), scale(B.w, R.r1.y));
+      const f3 sw = madd(scale(B.w, R.r1.y), A.w, R.r1.x);
       vr[0] = dot(n, dv);
       vr[1] = dot(t1, dv) - dot(t2, sw);
       vr[2] = dot(t2, dv) + dot(t1, sw);
@@ -1125,8 +1209,8 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
   const float invd[3] = {R.r2.x, R.r2.y, (R.joint || R.gen) ? R.r2.z : R.r2.y};
   float e = 0.0f;
   for (int k = 0; k < 3; ++k) {
-    const float wv = vr[k] + bias[k] + cfm * l[k];
-    const float pr = fminf(fmaxf(l[k] - wv * invd[k], lo[k]), hi[k]);
+    const float wv = fmaf(cfm, l[k], vr[k] + bias[k]);
+    const float pr = fminf(fmaxf(fmaf(-wv, invd[k], l[k]), lo[k]), hi[k]);
     e = fmaxf(e, fabsf(l[k] - pr) / invd[k]);
   }
   return e;
@@ -1135,7 +1219,7 @@ __device__ float copy_residual(const Rec& R, const Bod& A, const Bod& B, float c
 // Initial residual of a start (plain, or learned for contacts): apply it in
 // solve order, take the largest natural-map residual of the partition's rows,
 // then restore v~.  Uniform over the workgroup.
-template <int BS, bool kCaps, bool kSplit>
+template <int BS, bool kCaps, bool kSplit, bool kLds>
 __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int* coff, int r0, int nr,
                                 bool learned, float* red) {
   const int tid = threadIdx.x;
@@ -1147,9 +1231,9 @@ __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int*
       Rec R;
       load_rec<kCaps>(w, slot, R, packed);
       if (learned && !R.joint) R.lam = w.r_lamL[slot];
-      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, unused, slot, r0);
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, unused, nullptr, r0);
     }
-    __syncthreads();
+    vel_sync<kLds>();
   }
   float e = 0.0f;
   for (int slot = s0 + tid; slot < s0 + coff[ncol]; slot += BS) {
@@ -1163,13 +1247,42 @@ __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int*
   }
   e = block_max<BS>(e, red);
   load_replicas<BS, kSplit>(w, V, r0, nr);
-  __syncthreads();
+  vel_sync<kLds>();
   return e;
+}
+
+// One colour of a sweep, solved by the workgroup: each thread solves the
+// colour's slot at its own index (its record `cur`, loaded one colour ahead)
+// and, in colours larger than the workgroup, the slots BS, 2 BS, ... further
+// on; meanwhile the first slot of the next colour (local range [n0, n1), never
+// empty) is loaded into `nxt`.  Every lane issues that load, lanes past the
+// colour's end at its last slot, so each wave issues the same loads in every
+// pass and the wait for `cur` can leave the new loads in flight.  Ends with the
+// workgroup barrier between colours.
+template <int BS, bool kCaps, bool kLds>
+__device__ __forceinline__ void colour_pass(const WP& w, Vel V, const Slots& S, int b0, int b1, int n0, int n1,
+                                            bool prefetch, Rec& cur, bool& has_cur, Rec& nxt, bool& has_nxt,
+                                            int first, float& rl, int r0, bool packed) {
+  const int tid = threadIdx.x;
+  has_nxt = prefetch && n0 + tid < n1;
+  fetch_local<kCaps>(S, (uint32_t)min(n0 + tid, n1 - 1), nxt, packed);
+  if (has_cur) {
+    const uint32_t l = (uint32_t)(b0 + tid);
+    decode<kCaps>(cur, packed);
+    do_slot<true, kCaps, true, kLds>(w, V, cur, rl, reinterpret_cast<float4*>(S.lam + (l << 4)), r0);
+  }
+  for (int l = b0 + tid + first; l < b1; l += BS) {
+    Rec R;
+    fetch_local<kCaps>(S, (uint32_t)l, R, packed);
+    decode<kCaps>(R, packed);
+    do_slot<true, kCaps, true, kLds>(w, V, R, rl, reinterpret_cast<float4*>(S.lam + ((uint32_t)l << 4)), r0);
+  }
+  vel_sync<kLds>();
 }
 
 // Solve one partition with a workgroup of BS threads.  V holds its replica
 // velocities (LDS, or its slice of rep_v4 for the global variant).
-template <int BS, bool kCaps, bool kSplit>
+template <int BS, bool kCaps, bool kSplit, bool kLds>
 __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red) {
   const int tid = threadIdx.x;
   const int N = w.N;
@@ -1179,13 +1292,18 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   const int ncol = w.part_ncol[p];
   const bool packed = nr < kPackReps;  // uniform: ids from the impulses' fourth component
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
+  if (kLds && tid == 0) {
+    // the zero body at index -1 (a static second body in the sweeps)
+    V.p[-1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    V.p[V.stride - 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
   load_replicas<BS, kSplit>(w, V, r0, nr);
-  __syncthreads();
+  vel_sync<kLds>();
   float rl = 0.0f;
   if (w.learned) {
     // keep the learned start only when its initial residual is below the plain start's
-    const float rho_p = start_residual<BS, kCaps, kSplit>(w, V, s0, ncol, coff, r0, nr, false, red);
-    const float rho_l = start_residual<BS, kCaps, kSplit>(w, V, s0, ncol, coff, r0, nr, true, red);
+    const float rho_p = start_residual<BS, kCaps, kSplit, kLds>(w, V, s0, ncol, coff, r0, nr, false, red);
+    const float rho_l = start_residual<BS, kCaps, kSplit, kLds>(w, V, s0, ncol, coff, r0, nr, true, red);
     bool use = rho_l < rho_p;
     if (w.force_guard && w.part_force_guard[p] >= 0) use = w.part_force_guard[p] != 0;
     if (use)
@@ -1199,6 +1317,8 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
       w.part_rho0[2 * p] = rho_p;
       w.part_rho0[2 * p + 1] = rho_l;
     }
+    // the learned starts just stored are read below by other threads
+    __builtin_amdgcn_s_waitcnt(kWaitVmem0);
     __syncthreads();
   }
   // warm-start impulses enter in solve order
@@ -1207,9 +1327,9 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
     for (int slot = s0 + coff[c] + tid; slot < e; slot += BS) {
       Rec R;
       load_rec<kCaps>(w, slot, R, packed);
-      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, rl, slot, r0);
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, rl, nullptr, r0);
     }
-    __syncthreads();
+    vel_sync<kLds>();
   }
   // sweeps; the first slot of the next colour is loaded while the current colour is solved
   const int cap = w.forced ? w.part_force_iters[p] : w.max_iters;
@@ -1223,38 +1343,45 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   const int cv0 = coff[lane_id()];
   const int cv1 = coff[kColStride - 1];
   auto co = [&](int k) { return k < 64 ? __builtin_amdgcn_readlane(cv0, k) : cv1; };
-  Rec cur;
-  bool has_cur = ncol > 1 && co(0) + tid < co(1);
-  if (has_cur) fetch_rec<kCaps>(w, s0 + co(0) + tid, cur, packed);
-  // Nothing may still be in flight into `cur` when the loop is entered:
+  const Slots S = slots_of(w, s0);
+  // two record sets used in turn: one is solved while the next colour's first
+  // slot is loaded into the other, so no record is ever copied between them
+  Rec ra, rb;
+  bool ha = ncol > 1 && co(0) + tid < co(1), hb = false;
+  if (ncol > 0) fetch_local<kCaps>(S, (uint32_t)min(co(0) + tid, co(1) - 1), ra, packed);
+  // Nothing may still be in flight into the first set when the loop is entered:
   // otherwise the wait placed before its first use would also hold back the
-  // next colour's prefetch in every iteration.
+  // next colour's prefetch in every pass.
   __builtin_amdgcn_s_waitcnt(0);
-  while (it < cap) {
+  if (ncol == 0) {
+    // no rows: every sweep is empty (a zero residual stops adaptive sweeps after one)
+    it = (!w.forced && w.adaptive) ? min(cap, 1) : max(cap, 0);
+  } else if (cap > 0) {
+    int c = 0;
     rl = 0.0f;
-    for (int c = 0; c < ncol; ++c) {
-      const int cn = c + 1 < ncol ? c + 1 : 0;
-      const int b0 = co(c), b1 = co(c + 1), n0 = co(cn), n1 = co(cn + 1);
-      Rec nxt;
-      const bool has_nxt = ncol > 1 && n0 + tid < n1;
-      if (has_nxt) fetch_rec<kCaps>(w, s0 + n0 + tid, nxt, packed);
-      if (has_cur) {
-        decode<kCaps>(cur, packed);
-        do_slot<true, kCaps>(w, V, cur, rl, s0 + b0 + tid, r0);
+    // after colour c: the end of a sweep takes the residual and may stop
+    auto next_colour = [&]() {
+      if (++c < ncol) return false;
+      c = 0;
+      rho = block_max<BS>(rl, red);
+      rl = 0.0f;
+      ++it;
+      return it >= cap || (!w.forced && w.adaptive && rho <= w.tol);
+    };
+    for (;;) {
+      {
+        const int cn = c + 1 < ncol ? c + 1 : 0;
+        colour_pass<BS, kCaps, kLds>(w, V, S, co(c), co(c + 1), co(cn), co(cn + 1), ncol > 1, ra, ha, rb, hb,
+                                     first, rl, r0, packed);
       }
-      const int e = s0 + b1;
-      for (int slot = s0 + b0 + tid + first; slot < e; slot += BS) {
-        Rec R;
-        load_rec<kCaps>(w, slot, R, packed);
-        do_slot<true, kCaps>(w, V, R, rl, slot, r0);
+      if (next_colour()) break;
+      {
+        const int cn = c + 1 < ncol ? c + 1 : 0;
+        colour_pass<BS, kCaps, kLds>(w, V, S, co(c), co(c + 1), co(cn), co(cn + 1), ncol > 1, rb, hb, ra, ha,
+                                     first, rl, r0, packed);
       }
-      __syncthreads();
-      cur = nxt;
-      has_cur = has_nxt;
+      if (next_colour()) break;
     }
-    rho = block_max<BS>(rl, red);
-    ++it;
-    if (!w.forced && w.adaptive && rho <= w.tol) break;
   }
   // integrate and write the replica states
   const float h = w.dt;
@@ -1262,20 +1389,21 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   for (int r = tid; r < nr; r += BS) {
     const int b = w.rep_body_pm[r0 + r];
     const Bod B = ld_body(V, r);
-    const float x = w.st[b] + h * B.v.x;
-    const float y = w.st[N + b] + h * B.v.y;
-    const float z = w.st[2 * N + b] + h * B.v.z;
+    const float x = fmaf(h, B.v.x, w.st[b]);
+    const float y = fmaf(h, B.v.y, w.st[N + b]);
+    const float z = fmaf(h, B.v.z, w.st[2 * N + b]);
     float qw = w.st[3 * N + b], qx = w.st[4 * N + b], qy = w.st[5 * N + b], qz = w.st[6 * N + b];
     const float wx = B.w.x, wy = B.w.y, wz = B.w.z;
-    const float dw = -(wx * qx + wy * qy + wz * qz);
-    const float dx = wx * qw + (wy * qz - wz * qy);
-    const float dy = wy * qw + (wz * qx - wx * qz);
-    const float dz = wz * qw + (wx * qy - wy * qx);
-    qw += 0.5f * h * dw;
-    qx += 0.5f * h * dx;
-    qy += 0.5f * h * dy;
-    qz += 0.5f * h * dz;
-    const float nn = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    const float dw = -fmaf(wz, qz, fmaf(wy, qy, wx * qx));
+    const float dx = fmaf(wx, qw, fmaf(wy, qz, -(wz * qy)));
+    const float dy = fmaf(wy, qw, fmaf(wz, qx, -(wx * qz)));
+    const float dz = fmaf(wz, qw, fmaf(wx, qy, -(wy * qx)));
+    const float hh = 0.5f * h;
+    qw = fmaf(hh, dw, qw);
+    qx = fmaf(hh, dx, qx);
+    qy = fmaf(hh, dy, qy);
+    qz = fmaf(hh, dz, qz);
+    const float nn = 1.0f / sqrtf(fmaf(qz, qz, fmaf(qy, qy, fmaf(qx, qx, qw * qw))));
     const float out[13] = {x, y, z, qw * nn, qx * nn, qy * nn, qz * nn, B.v.x, B.v.y, B.v.z, B.w.x, B.w.y, B.w.z};
 #pragma unroll
     for (int k = 0; k < 13; ++k) {
@@ -1325,8 +1453,10 @@ __global__ __launch_bounds__(BS) void k_pgs(WP w) {
     const int p = w.part_order[k];
     const int nr = w.part_rep_off[p + 1] - w.part_rep_off[p];
     if (kLds == (nr <= kReps)) {  // otherwise the other variant handles this partition
-      const Vel V = kLds ? Vel{sm4, kReps} : Vel{w.rep_v4 + w.part_rep_off[p], w.Rcap};
-      solve_partition<BS, kCaps, kSplit>(w, p, V, coff, red);
+      // LDS: [0][v, 1/m of kReps replicas][0][w, 1/I of kReps replicas], indexed from the
+      // first replica, so index -1 of either array is a zero entry
+      const Vel V = kLds ? Vel{sm4 + 1, kReps + 1} : Vel{w.rep_v4 + w.part_rep_off[p], w.Rcap};
+      solve_partition<BS, kCaps, kSplit, kLds>(w, p, V, coff, red);
     }
     if (!w.pgs_persistent) break;
   }
@@ -1487,38 +1617,39 @@ constexpr int kCommitBS = 1024;
 
 __global__ __launch_bounds__(kCommitBS) void k_commit(WP w) {
   __shared__ int failed_s;
-  __shared__ long long part[4][kCommitBS / 64];
+  __shared__ long long part[5][kCommitBS / 64];
   if (threadIdx.x == 0) failed_s = w.scal[SC_FLAGS] != 0;
   __syncthreads();
   if (failed_s) return;
   // the cache written by k_cache is indexed by this step's partition ranges
   for (int g = threadIdx.x; g <= w.G; g += kCommitBS) w.wc_off[g] = w.part_copy_off[g];
   int mx = 0;
-  long long unconv = 0, bytes = 0, sweeps = 0;
+  long long unconv = 0, bytes = 0, sweeps = 0, ops = 0;
   for (int g = threadIdx.x; g < w.G; g += kCommitBS) {
     const int it = w.part_iters[g];
     mx = max(mx, it);
     if (w.adaptive && !w.forced && it >= w.max_iters && w.part_resid[g] > w.tol) ++unconv;
     const int64_t nj = w.mc_psize[1][g], nc = w.mc_psize[2][g], ns = w.part_nstatic[g];
     bytes += (int64_t)it * ((nc - ns) * kBytesDynDyn + ns * kBytesStatic + nj * kBytesJoint);
+    ops += (int64_t)it * ((nc - ns) * kOpsDynDyn + ns * kOpsStatic + nj * kOpsJoint);
     sweeps += it;
   }
-  long long v[4] = {mx, unconv, bytes, sweeps};
+  long long v[5] = {mx, unconv, bytes, sweeps, ops};
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 5; ++k)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
       const long long o = __shfl_xor(v[k], d, 64);
       v[k] = k == 0 ? max(v[k], o) : v[k] + o;
     }
   if (lane_id() == 0)
-    for (int k = 0; k < 4; ++k) part[k][threadIdx.x >> 6] = v[k];
+    for (int k = 0; k < 5; ++k) part[k][threadIdx.x >> 6] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long t[4] = {0, 0, 0, 0};
+    long long t[5] = {0, 0, 0, 0, 0};
     for (int i = 0; i < kCommitBS / 64; ++i) {
       t[0] = max(t[0], part[0][i]);
-      for (int k = 1; k < 4; ++k) t[k] += part[k][i];
+      for (int k = 1; k < 5; ++k) t[k] += part[k][i];
     }
     w.scal[SC_PREV_NCOPY] = w.part_copy_off[w.G];
     w.scal[SC_COMMITTED] += 1;
@@ -1528,6 +1659,7 @@ __global__ __launch_bounds__(kCommitBS) void k_commit(WP w) {
     w.stat_i64[3] += t[3];
     w.stat_i64[4] += 1;
     w.stat_i64[5] += t[1] > 0 ? 1 : 0;
+    w.stat_i64[6] += t[4];
   }
 }
 
@@ -1652,7 +1784,7 @@ namespace {
 template <int BS, int R>
 hipError_t set_attrs_t() {
   hipError_t e = hipSuccess;
-  const int lds = 2 * R * (int)sizeof(float4);
+  const int lds = 2 * (R + 1) * (int)sizeof(float4);
   const void* fns[4] = {(const void*)k_pgs<BS, R, true, false, false>, (const void*)k_pgs<BS, R, true, true, false>,
                         (const void*)k_pgs<BS, R, true, false, true>, (const void*)k_pgs<BS, R, true, true, true>};
   for (const void* f : fns)
@@ -1662,7 +1794,7 @@ hipError_t set_attrs_t() {
 
 template <int BS, int R>
 hipError_t occupancy_t(bool caps, int* per_cu_lds, int* per_cu_glob) {
-  const size_t lds = 2 * (size_t)R * sizeof(float4);
+  const size_t lds = 2 * ((size_t)R + 1) * sizeof(float4);
   hipError_t e;
   if (caps) {
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, true, false>, BS, lds)))
@@ -1676,7 +1808,7 @@ hipError_t occupancy_t(bool caps, int* per_cu_lds, int* per_cu_glob) {
 
 template <int BS, int R>
 hipError_t launch_pgs_t(const WP& w, hipStream_t s) {
-  const size_t lds = 2 * (size_t)R * sizeof(float4);
+  const size_t lds = 2 * ((size_t)R + 1) * sizeof(float4);
   const int g0 = w.pgs_persistent ? std::min(w.G, w.pgs_grid[0]) : w.G;
   const int g1 = w.pgs_persistent ? std::min(w.G, w.pgs_grid[1]) : w.G;
   hipError_t e;

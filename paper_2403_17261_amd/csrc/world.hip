@@ -1104,6 +1104,7 @@ ovl_status ovl_get_counters(ovl_world* w, ovl_counters* out) {
   out->pgs_launches = w->pgs_launches;
   out->pgs_ms = w->pgs_ms;
   out->steps_capped = c[5];
+  out->pgs_ops = c[6];
   return OVL_OK;
 }
 

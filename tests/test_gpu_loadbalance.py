@@ -4,9 +4,10 @@ bridge test of Alg. 7) against the oracle.
 The carried worker sets are an input of a step; every case hands the same
 sets to both sides and compares the sets the step produces bit for bit, then
 the rest of the step (replica tables, weights, velocities) as every other
-parity test does.  Start states and sets come from oracle runs, except in the
-trajectory test, which compares one step after a GPU run from that run's own
-state and sets.
+parity test does.  Start states and sets come from the scene or from oracle
+runs (oracle.run_lb); no oracle input is read back from the library.  The
+graph-replay test checks replayed steps against eager GPU steps, then one step
+against the oracle from the oracle's own run of the same length.
 
 Cases: the Figure 9 scenarios on hand-placed spheres, including the chain at
 growth depths 0 to 3 and an isolated collision over two steps; a settling bowl
