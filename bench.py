@@ -1,12 +1,20 @@
 #!/usr/bin/env python3
-"""Benchmark: body-steps/s at projected Gauss-Seidel residual <= 1e-4 (plain warm start).
+"""Benchmark: body-steps/s at projected Gauss-Seidel residual <= 1e-4, learned
+against plain warm start.
 
 Default workload (--workload tower): the 100,000-sphere tower collapse, a
 50x50x40 lattice of spheres (r = 0.25 m, density 1000 kg/m^3, jitter
 U(+-0.005) m) on a ground plane, mu = 0.5, h = 1/60 s, 64 column partitions
 (8x8) with a 2-hop overlap, geodesic search depth 4, adaptive sweeps to a
-residual of 1e-4 m/s with a cap of 1000, 300 steps from the initial state
-(the warm-up steps run first and the state is then reset).
+residual of 1e-4 m/s with a cap of 1000, the first --steps steps from the
+initial state (the warm-up steps run first and the state is then reset).
+Plain and learned warm starts are timed at 1e-4 and again at the looser
+tolerances 1e-2, 3e-3 and 1e-3 (the ladder); the line states the share of
+partition-steps that reach each tolerance before the cap, and compares the
+two starts at the tightest tolerance both reach in at least 95% of
+partition-steps.  The other four configurations (the 64-sphere lattice, the
+bowl pile, the chains and the 512 batched bowls) are timed at their fixed
+sweep counts over their stated step counts and reported beside the headline.
 
 --workload bowl: the 20,000-sphere bowl pile (8 k-means partitions recomputed
 every 10 steps, 2-hop overlap), 1000 steps.
@@ -32,10 +40,13 @@ step, all in one world: the autotuned, graph-replayed launch against the
 default launch and against a loop that steps one world per scene.
 
 One GPU only.  Prints one JSON line.  The roofline entry is for the
-Gauss-Seidel kernel: algorithmic bytes of all sweeps of the timed steps (per
-sweep and constraint copy: 220 B for two bodies, 164 B with a static body,
-192 B for a joint) over its summed duration from HIP events recorded on the
-stream the kernel runs on.
+Gauss-Seidel kernel, whose binding resource is vector-instruction issue on the
+compute units that hold a partition: the algorithmic FP32 operations of all
+sweeps of the timed steps (per sweep and constraint copy: 88 for a sphere
+contact between two bodies, 74 with a static body, 63 for a ball joint) over
+the kernel's summed duration from HIP events recorded on the stream it runs
+on, against the chip's VALU issue rate without packed FP32.  The algorithmic
+byte rate (220 / 164 / 192 B per copy and sweep) is reported beside it.
 """
 import argparse
 import hashlib
@@ -49,11 +60,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
 # interface coupling modes (the library's OVL_COUPLING_* values)
 COUPLING_NAMES = {0: "none", 1: "previous-step impulses", 2: "mass splitting"}
 COUPLING_FLAGS = {"none": 0, "impulse": 1, "split": 2}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pgs_traffic.json")
 SOLVER_SRC = os.path.join(ROOT, "paper_2403_17261_amd", "csrc", "solve.hip")
 
 
@@ -64,18 +73,6 @@ def log(*a):
 def solver_hash():
     with open(SOLVER_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
-def measured_traffic():
-    """HBM bytes per solver launch from committed rocprofv3 counters, if they match this kernel."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("solver_sha") != solver_hash():
-        return None
-    return t.get("bytes_per_launch")
 
 
 def run_loop(w, sc, steps, state0, owner0, cent0, rebalance_iters=3):
@@ -97,8 +94,28 @@ def run_loop(w, sc, steps, state0, owner0, cent0, rebalance_iters=3):
     return owner, cent
 
 
-def cpu_baseline(workload, n_steps, tol, cap):
-    """The oracle (single thread, double precision) on a bounded sample of the workload."""
+def host_cpu():
+    """CPU model, online CPUs and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc_online": os.cpu_count(), "nproc_usable": usable}
+
+
+def cpu_baseline(workload, n_steps, tol, cap, max_threads=16):
+    """The oracle (double precision) on a bounded sample of the workload, on one
+    thread and on T = min(partitions, usable cores, max_threads) threads, one
+    partition per thread at a time (the paper's worker per core)."""
     import oracle
     from paper_2403_17261_amd import scenes
 
@@ -106,7 +123,7 @@ def cpu_baseline(workload, n_steps, tol, cap):
     if workload == "tower":
         # a 25x25x40 sub-tower in 4x4 columns: partitions of the benchmark's size, from t = 0
         sc = scenes.config5(0, nx=25, ny=25, nz=40, cols=4)
-        st, owner, o = sc.state, sc.owner, None
+        st0, owner, o0 = sc.state, sc.owner, None
         what = (f"the first {n_steps} steps of a 25x25x40 sub-tower (25,000 spheres, 4x4 column partitions of the "
                 f"benchmark's partition size) from t = 0")
     else:
@@ -115,21 +132,35 @@ def cpu_baseline(workload, n_steps, tol, cap):
             return None
         d = np.load(path)
         sc = scenes.config2(0)
-        st, owner = d["state"], d["owner"]
-        o = oracle.step(sc, state=st, owner=owner, **kw)           # untimed: fills the warm-start cache
-        st = o["state"].astype(np.float32)
+        owner = d["owner"]
+        o0 = oracle.step(sc, state=d["state"], owner=owner, **kw)         # untimed: fills the warm-start cache
+        st0 = o0["state"].astype(np.float32)
         what = f"{n_steps} steps of the 20,000-sphere bowl pile from its oracle-computed state at step 300"
-    t0 = time.perf_counter()
-    sweeps = 0
-    for _ in range(n_steps):
-        o = oracle.step(sc, state=st, owner=owner, cache=o, **kw)
-        st = o["state"].astype(np.float32)
-        sweeps += int(o["max_iters"])
-    dt = time.perf_counter() - t0
+    host = host_cpu()
+    G = int(sc.parts_per_scene.sum())
+    T = max(1, min(G, host["nproc_usable"], max_threads))
+
+    def leg(threads):
+        st, o = st0, o0
+        t0 = time.perf_counter()
+        sweeps = 0
+        for _ in range(n_steps):
+            o = oracle.step(sc, state=st, owner=owner, cache=o, threads=threads, **kw)
+            st = o["state"].astype(np.float32)
+            sweeps += int(o["max_iters"])
+        dt = time.perf_counter() - t0
+        return {"value": sc.n_bodies * n_steps / dt, "unit": "body-steps/s", "threads": threads,
+                "secs": round(dt, 2), "sweeps_per_step": sweeps / n_steps}
+
+    one = leg(1)
+    many = leg(T) if T > 1 else one
     return {
-        "value": sc.n_bodies * n_steps / dt, "unit": "body-steps/s", "cores": 1, "kind": "oracle",
-        "sample": f"oracle (double precision, one thread, adaptive sweeps to {tol:g}, cap {cap}): {what}; "
-                  f"mean {sweeps / n_steps:.0f} sweeps per step, {dt:.1f} s",
+        "value": many["value"], "unit": "body-steps/s", "cores": T, "kind": "oracle",
+        "sample": f"oracle (double precision, adaptive sweeps to {tol:g}, cap {cap}): {what}; {G} partitions "
+                  f"solved on {T} threads, one partition per thread at a time (the paper's worker per core); "
+                  f"contacts, graph, weights and blending sequential; mean {many['sweeps_per_step']:.0f} sweeps "
+                  f"per step (largest partition), {many['secs']:.1f} s",
+        "single_thread": one, "worker_per_core": many, **host,
     }
 
 
@@ -253,7 +284,7 @@ def bench_bowl_lb(args):
             raise RuntimeError("not every step committed")
         r = {"secs": secs, "value": sc.n_bodies * steps / secs, "ms_per_step": 1e3 * secs / steps,
              "pgs_ms": c1["pgs_ms"] - c0["pgs_ms"], "pgs_launches": c1["pgs_launches"] - c0["pgs_launches"],
-             "pgs_bytes": c1["pgs_bytes"] - c0["pgs_bytes"],
+             "pgs_bytes": c1["pgs_bytes"] - c0["pgs_bytes"], "pgs_ops": c1["pgs_ops"] - c0["pgs_ops"],
              "sweeps_mean": (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / steps,
              "unconverged": c1["unconverged_total"] - c0["unconverged_total"]}
         log(f"[bowl-lb {'on' if lb else 'off'}] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step, "
@@ -295,7 +326,7 @@ def bench_bowl_lb(args):
     on["exact"] = exact_replay(w, True)
     w.close()
     pgs_ms, pgs_launches, pgs_bytes = on["pgs_ms"], on["pgs_launches"], on["pgs_bytes"]
-    achieved = pgs_bytes / (pgs_ms * 1e-3) / 1e9 if pgs_ms > 0 else 0.0
+    ops_rate = on["pgs_ops"] / (pgs_ms * 1e-3) / 1e12 if pgs_ms > 0 else 0.0
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_lb(sc, args.tol, args.cap)
@@ -332,10 +363,12 @@ def bench_bowl_lb(args):
                                             "the body's mass and inertia"},
         },
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bound": "alu", "achieved": ops_rate, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": ops_rate / VALU_PEAK_TOPS, "traffic": None,
             "kernel": "k_pgs (coloured projected Gauss-Seidel, one workgroup per partition)",
             "launches": int(pgs_launches), "ms_per_launch": pgs_ms / max(1, pgs_launches),
+            "alg_ops_per_launch": on["pgs_ops"] / max(1, pgs_launches),
+            "busy_cus": min(G, N_CUS),
             "alg_bytes_per_launch": pgs_bytes / max(1, pgs_launches),
         },
         "cpu_baseline": cpu,
@@ -483,6 +516,267 @@ def per_scene_loop(sc, p, args, timed):
     return r
 
 
+LADDER = (1e-2, 3e-3, 1e-3, 1e-4)
+# VALU issue of MI355X without packed FP32: 256 compute units, each issuing one
+# wave64 vector instruction per clock (four 16-lane SIMDs, four clocks each),
+# at 2.4 GHz: 256 * 64 * 2.4e9 single-precision lane operations per second.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+N_CUS = 256
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "pgs_counters.json")
+
+
+def measured_counters():
+    """rocprofv3 counters of the solver kernel on this workload (profiles/), if
+    they were taken from this solver source; else None."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return t if t.get("solver_sha") == solver_hash() else None
+
+
+def reset_run(w, sc, owner0):
+    w.write_state(sc.state, keep_cache=False)
+    w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+
+
+def timed_run(w, sc, steps, owner0, cent0):
+    """steps steps from the scene's initial state (warm-start cache cleared), timed
+    with the device idle on both sides; solver launches timed with HIP events."""
+    import torch
+
+    reset_run(w, sc, owner0)
+    w.profile(True)
+    c0 = w.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_loop(w, sc, steps, sc.state, owner0, cent0)
+    w.sync()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    c1 = w.counters()
+    w.profile(False)
+    done = c1["steps"] - c0["steps"]
+    if done != steps:
+        raise RuntimeError(f"only {done} of {steps} steps committed")
+    G = int(np.sum(sc.parts_per_scene))
+    d = {k: c1[k] - c0[k] for k in ("pgs_ms", "pgs_launches", "pgs_bytes", "pgs_ops", "sweeps_max_total",
+                                     "sweeps_part_total", "unconverged_total", "steps_capped")}
+    return {"secs": secs, "value": sc.n_bodies * steps / secs, "ms_per_step": 1e3 * secs / steps,
+            "pgs_ms": d["pgs_ms"], "pgs_launches": d["pgs_launches"], "pgs_bytes": d["pgs_bytes"],
+            "pgs_ops": d["pgs_ops"], "sweeps_mean": d["sweeps_max_total"] / steps,
+            "sweeps_part_mean": d["sweeps_part_total"] / (steps * G), "unconverged": d["unconverged_total"],
+            "steps_capped": d["steps_capped"], "partition_steps": steps * G,
+            "pct_converged": 100.0 * (1.0 - d["unconverged_total"] / (steps * G))}
+
+
+def rung_summary(r):
+    return {"body_steps_per_s": r["value"], "ms_per_step": r["ms_per_step"],
+            "partition_sweeps_per_step": round(r["sweeps_part_mean"], 2),
+            "largest_partition_sweeps_per_step": round(r["sweeps_mean"], 2),
+            "partition_steps_converged_pct": round(r["pct_converged"], 2),
+            "steps_with_a_capped_partition_pct": round(100.0 * r["steps_capped"] / max(1, r["steps"]), 2)}
+
+
+def bench_tower(args):
+    """The headline: body-steps/s at residual <= tol (cap) on the tower collapse,
+    learned and plain warm starts, with a ladder of looser tolerances."""
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    sc = scenes.config5(0) if args.workload == "tower" else scenes.config2(0)
+    if args.steps is None:
+        args.steps = sc.steps
+    mode = ovl.MODE_ADAPTIVE if args.mode == "adaptive" else ovl.MODE_FIXED
+    cap = args.cap if mode == ovl.MODE_ADAPTIVE else sc.iters
+    G = int(np.sum(sc.parts_per_scene))
+    owner0 = sc.owner.copy()
+    cent0 = sc.centroids[0].copy() if sc.rebalance_every else None
+    modes = ["plain", "learned"] if args.warm == "both" else [args.warm]
+    weights = None
+    if "learned" in modes:
+        if os.path.exists(args.weights):
+            weights = np.load(args.weights, allow_pickle=False)["params"]
+        else:
+            log(f"no network weights at {args.weights}: timing the plain warm start only")
+            modes = ["plain"]
+    ladder = [t for t in LADDER if t != args.tol] if (mode == ovl.MODE_ADAPTIVE and not args.no_ladder) else []
+    runs, rungs = {}, {}
+    for mode_name in modes:
+        p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN,
+                            coupling=COUPLING_FLAGS[args.coupling])
+        w = ovl.World(sc, p)
+        w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        if mode_name == "learned":
+            w.set_warmstart(ovl.WARM_LEARNED, weights)
+        log(f"[{mode_name}] warm-up: {args.warmup} steps")
+        run_loop(w, sc, args.warmup, sc.state, owner0, cent0)
+        w.sync()
+        log(f"[{mode_name}] timed: {args.steps} steps at tol {args.tol:g}, cap {cap}")
+        r = timed_run(w, sc, args.steps, owner0, cent0)
+        r["steps"] = args.steps
+        # untimed: the same run again, the exact residual of every exact_every-th step
+        exact = []
+        if args.exact_every and mode == ovl.MODE_ADAPTIVE:
+            reset_run(w, sc, owner0)
+            for _ in range(args.exact_every, args.steps + 1, args.exact_every):
+                w.step(args.exact_every - 1)
+                exact.append(w.step(1, stats=True, exact=True)["resid_exact"])
+        r["exact_sampled"] = exact
+        r["last"] = w.step(0, stats=True)
+        runs[mode_name] = r
+        log(f"[{mode_name}] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step, solver "
+            f"{r['pgs_ms'] / max(1, r['pgs_launches']):.3f} ms/launch, partition sweeps/step "
+            f"{r['sweeps_part_mean']:.1f}, converged {r['pct_converged']:.1f}%")
+        rungs[mode_name] = {args.tol: rung_summary(r)}
+        for tol in ladder:
+            w.set_params(tol=tol)
+            q = timed_run(w, sc, args.steps, owner0, cent0)
+            q["steps"] = args.steps
+            rungs[mode_name][tol] = rung_summary(q)
+            log(f"[{mode_name} tol {tol:g}] {q['value']:.3e} body-steps/s, partition sweeps/step "
+                f"{q['sweeps_part_mean']:.1f}, converged {q['pct_converged']:.1f}%")
+        w.close()
+    head_name = "learned" if "learned" in runs else "plain"
+    head = runs[head_name]
+    # equal accuracy: the tightest tolerance that both starts reach in >= 95% of partition-steps
+    equal = None
+    if len(rungs) == 2:
+        both = [t for t in sorted(rungs["plain"]) if t in rungs["learned"] and
+                rungs["plain"][t]["partition_steps_converged_pct"] >= 95.0 and
+                rungs["learned"][t]["partition_steps_converged_pct"] >= 95.0]
+        if both:
+            t = both[0]
+            pl, le = rungs["plain"][t], rungs["learned"][t]
+            equal = {"tol": t, "plain": pl, "learned": le,
+                     "learned_over_plain_body_steps_per_s": le["body_steps_per_s"] / pl["body_steps_per_s"],
+                     "learned_over_plain_partition_sweeps": (le["partition_sweeps_per_step"] /
+                                                             max(1e-9, pl["partition_sweeps_per_step"]))}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: {args.cpu_steps} oracle steps, one thread and one thread per partition")
+        cpu = cpu_baseline(args.workload, args.cpu_steps, args.tol, args.cap)
+    others = None if args.no_configs else other_configs()
+    pgs_ms, launches = head["pgs_ms"], max(1, head["pgs_launches"])
+    ms_launch = pgs_ms / launches
+    ops_rate = head["pgs_ops"] / (pgs_ms * 1e-3) / 1e12 if pgs_ms > 0 else 0.0
+    busy = min(G, N_CUS)
+    cnt = measured_counters()
+    capped = head["steps_capped"] > 0
+    out = {
+        "metric": "body-steps/s at PGS residual <=1e-4; learned warm-start vs plain PGS",
+        "value": head["value"],
+        "unit": "body-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"tower collapse: 50x50x40 spheres r 0.25 m, density 1000, jitter 0.005 m, mu 0.5, "
+                         f"h 1/60 s, 64 column partitions, 2-hop overlap, beta 4, first {args.steps} steps"
+                         if args.workload == "tower" else
+                         f"bowl pile: 20,000 spheres r~U(0.2,0.5) m, density 1000, five-plane bowl, mu 0.6, "
+                         f"h 1/60 s, 8 k-means partitions (recomputed every 10 steps), 2-hop overlap, beta 4, "
+                         f"first {args.steps} steps from the initial drop"),
+            "n_bodies": sc.n_bodies, "partitions": G, "halo_k": sc.halo_k, "beta": sc.beta,
+            "sweeps": f"{args.mode}, tol {args.tol:g}, cap {cap}",
+            "warm_start": "learned (guarded per partition)" if head_name == "learned" else "plain",
+            "interface_coupling": COUPLING_NAMES[COUPLING_FLAGS[args.coupling]],
+            "accuracy": {
+                "capped": capped,
+                "label": (f"capped at {cap} sweeps: {head['pct_converged']:.1f}% of partition-steps reach "
+                          f"residual {args.tol:g}; the rest stop at the cap" if capped else
+                          f"every partition-step reaches residual {args.tol:g} within {cap} sweeps"),
+                "partition_steps_converged_pct": round(head["pct_converged"], 2),
+                "unconverged_partition_steps": int(head["unconverged"]),
+                "partition_steps": int(head["partition_steps"]),
+                "exact_residual_sampled_mean": float(np.mean(head["exact_sampled"])) if head["exact_sampled"] else None,
+                "exact_residual_sampled_median": (float(np.median(head["exact_sampled"]))
+                                                  if head["exact_sampled"] else None),
+                "exact_residual_samples": len(head["exact_sampled"]),
+            },
+            "learned_vs_plain": {k: {**rung_summary(v),
+                                     "exact_residual_sampled_mean": (float(np.mean(v["exact_sampled"]))
+                                                                     if v["exact_sampled"] else None)}
+                                 for k, v in runs.items()},
+            "tolerance_ladder": {k: {f"{t:g}": v[t] for t in sorted(v, reverse=True)} for k, v in rungs.items()},
+            "equal_accuracy": equal,
+            "last_step": {k: head["last"][k] for k in ("n_contacts", "n_copies", "n_replicas", "n_overlap",
+                                                       "max_colours")},
+            "other_configs": others,
+        },
+        "roofline": {
+            "bound": "alu", "achieved": ops_rate, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": ops_rate / VALU_PEAK_TOPS,
+            "traffic": None if cnt is None else cnt.get("hbm_bytes_per_launch"),
+            "kernel": "k_pgs (coloured projected Gauss-Seidel, one workgroup per partition)",
+            "peak_basis": "FP32 vector lane operations: 256 CUs x 64 lanes x 2.4 GHz (one wave64 VALU "
+                          "instruction per CU per clock, no packed FP32)",
+            "achieved_basis": "algorithmic FP32 operations of the sweeps (88 per sphere-contact copy, 74 with a "
+                              "static body, 63 per ball joint) over the kernel's HIP-event time",
+            "launches": int(head["pgs_launches"]), "ms_per_launch": ms_launch,
+            "alg_ops_per_launch": head["pgs_ops"] / launches,
+            "busy_cus": busy, "frac_of_busy_cus": ops_rate / (VALU_PEAK_TOPS * busy / N_CUS),
+            "alg_bytes_per_launch": head["pgs_bytes"] / launches,
+            "alg_bytes_rate_gbs": head["pgs_bytes"] / (pgs_ms * 1e-3) / 1e9 if pgs_ms > 0 else 0.0,
+            "measured": None if cnt is None else cnt.get("summary"),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def other_configs():
+    """Fixed-sweep throughput of the four other configurations, each over its
+    stated number of steps from its initial state (after 10 warm-up steps)."""
+    import torch
+
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    out = {}
+    for name, make in (("small", scenes.config1), ("bowl", scenes.config2), ("chains", scenes.config3),
+                       ("batched", scenes.config4)):
+        sc = make(0)
+        p = ovl.make_params(dt=sc.dt, max_iters=sc.iters, mode=ovl.MODE_FIXED, warmstart=ovl.WARM_PLAIN)
+        w = ovl.World(sc, p)
+        owner0 = sc.owner.copy()
+        batched = name == "batched"
+        cent0 = sc.centroids[0].copy() if (sc.rebalance_every and not batched) else None
+        if batched:
+            w.set_launch(graph=1)
+        w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        w.step(10)
+        w.sync()
+        reset_run(w, sc, owner0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if batched:
+            w.step(sc.steps)         # partitions fixed at the start (one graph-replayed world)
+        else:
+            run_loop(w, sc, sc.steps, sc.state, owner0, cent0)
+        w.sync()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        st = w.step(0, stats=True)
+        w.close()
+        out[name] = {"n_bodies": sc.n_bodies, "partitions": int(np.sum(sc.parts_per_scene)),
+                     "halo_k": sc.halo_k, "sweeps": sc.iters, "steps": sc.steps, "dt": sc.dt,
+                     "body_steps_per_s": sc.n_bodies * sc.steps / secs, "ms_per_step": 1e3 * secs / sc.steps,
+                     "contacts_last": st["n_contacts"], "copies_last": st["n_copies"],
+                     "note": ("k-means owners recomputed on the host every 10 steps (inside the timed loop)"
+                              if cent0 is not None else ("one world, graph-replayed steps, default launch"
+                                                         if batched else "owners fixed"))}
+        log(f"[{name}] {out[name]['body_steps_per_s']:.3e} body-steps/s, {out[name]['ms_per_step']:.3f} ms/step")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,6 +788,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cap", type=int, default=1000)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-ladder", action="store_true", help="tower/bowl: time only the head tolerance")
+    ap.add_argument("--no-configs", action="store_true", help="tower/bowl: leave out the other configurations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm", choices=["plain", "learned", "both"], default="both",
                     help="warm start of the timed run; 'both' times plain then learned and reports learned")
@@ -503,7 +799,7 @@ def main():
     ap.add_argument("--coupling", nargs="?", const="impulse", default="none", choices=["none", "impulse", "split"],
                     help="tower/bowl: interface coupling, by the previous step's impulses of cut constraints "
                          "(impulse) or by splitting the mass of overlap bodies (split)")
-    ap.add_argument("--exact-every", type=int, default=25,
+    ap.add_argument("--exact-every", type=int, default=5,
                     help="tower/bowl: after timing, replay the run untimed with the exact residual every this many "
                          "steps (0: off)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -543,139 +839,7 @@ def main():
         return
     if args.warmup is None:
         args.warmup = 10
-    sc = scenes.config5(0) if args.workload == "tower" else scenes.config2(0)
-    if args.steps is None:
-        args.steps = sc.steps
-    mode = ovl.MODE_ADAPTIVE if args.mode == "adaptive" else ovl.MODE_FIXED
-    cap = args.cap if mode == ovl.MODE_ADAPTIVE else sc.iters
-    p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=mode, tol=args.tol, warmstart=ovl.WARM_PLAIN,
-                        coupling=COUPLING_FLAGS[args.coupling])
-    owner0 = sc.owner.copy()
-    cent0 = sc.centroids[0].copy() if sc.rebalance_every else None
-    weights = None
-    modes = ["plain", "learned"] if args.warm == "both" else [args.warm]
-    if "learned" in modes:
-        if os.path.exists(args.weights):
-            weights = np.load(args.weights, allow_pickle=False)["params"]
-        else:
-            log(f"no network weights at {args.weights}: timing the plain warm start only")
-            modes = ["plain"]
-    runs = {}
-    for mode_name in modes:
-        w = ovl.World(sc, p)
-        w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
-        if mode_name == "learned":
-            w.set_warmstart(ovl.WARM_LEARNED, weights)
-        log(f"[{mode_name}] warm-up: {args.warmup} steps")
-        run_loop(w, sc, args.warmup, sc.state, owner0, cent0)
-        w.sync()
-        # reset to the scene's initial state: the timed steps are the run's first `steps` steps
-        w.write_state(sc.state, keep_cache=False)
-        w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
-        w.profile(True)
-        c0 = w.counters()
-        log(f"[{mode_name}] timed: {args.steps} steps")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_loop(w, sc, args.steps, sc.state, owner0, cent0)
-        w.sync()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        c1 = w.counters()
-        last = w.step(0, stats=True)
-        # untimed: the exact natural-map residual of the step after the timed ones
-        nxt = w.step(1, stats=True, exact=True)
-        # untimed: the same run again, the exact residual of every 25th step
-        exact = []
-        if args.exact_every:
-            w.write_state(sc.state, keep_cache=False)
-            w.set_partitions(owner0, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
-            for t in range(args.exact_every, args.steps + 1, args.exact_every):
-                w.step(args.exact_every - 1)
-                exact.append(w.step(1, stats=True, exact=True)["resid_exact"])
-        secs = t1 - t0
-        steps_done = c1["steps"] - c0["steps"]
-        if steps_done != args.steps:
-            raise RuntimeError(f"only {steps_done} of {args.steps} steps committed")
-        r = {"secs": secs, "value": sc.n_bodies * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
-             "pgs_ms": c1["pgs_ms"] - c0["pgs_ms"], "pgs_launches": c1["pgs_launches"] - c0["pgs_launches"],
-             "pgs_bytes": c1["pgs_bytes"] - c0["pgs_bytes"],
-             "sweeps_mean": (c1["sweeps_max_total"] - c0["sweeps_max_total"]) / max(1, steps_done),
-             "sweeps_part_mean": (c1["sweeps_part_total"] - c0["sweeps_part_total"]) / max(1, steps_done * w.G),
-             "unconverged": c1["unconverged_total"] - c0["unconverged_total"], "last": last,
-             "steps_capped": c1["steps_capped"] - c0["steps_capped"], "exact_next": nxt["resid_exact"],
-             "exact_sampled": exact}
-        r["achieved"] = r["pgs_bytes"] / (r["pgs_ms"] * 1e-3) / 1e9 if r["pgs_ms"] > 0 else 0.0
-        runs[mode_name] = r
-        log(f"[{mode_name}] {r['value']:.3e} body-steps/s, {r['ms_per_step']:.3f} ms/step, solver "
-            f"{r['pgs_ms'] / max(1, r['pgs_launches']):.3f} ms/launch, {r['achieved']:.1f} GB/s algorithmic, "
-            f"sweeps/step {r['sweeps_mean']:.1f} (partition mean {r['sweeps_part_mean']:.1f}), "
-            f"unconverged {r['unconverged']}")
-        w.close()
-    head = runs["learned"] if "learned" in runs else runs["plain"]
-    secs = head["secs"]
-    pgs_ms, pgs_launches, pgs_bytes = head["pgs_ms"], head["pgs_launches"], head["pgs_bytes"]
-    achieved = head["achieved"]
-    traffic = measured_traffic()
-    sweeps_mean = head["sweeps_mean"]
-    unconv = head["unconverged"]
-    last = head["last"]
-    value = head["value"]
-    cpu = None
-    if not args.no_cpu_baseline:
-        log(f"cpu baseline: {args.cpu_steps} oracle steps")
-        cpu = cpu_baseline(args.workload, args.cpu_steps, args.tol, args.cap)
-    out = {
-        "metric": "body-steps/s at PGS residual <=1e-4; learned warm-start vs plain PGS",
-        "value": value,
-        "unit": "body-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * secs / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": (f"tower collapse: 50x50x40 spheres r 0.25 m, density 1000, jitter 0.005 m, mu 0.5, "
-                         f"h 1/60 s, 64 column partitions, 2-hop overlap, beta 4, first {args.steps} steps"
-                         if args.workload == "tower" else
-                         f"bowl pile: 20,000 spheres r~U(0.2,0.5) m, density 1000, five-plane bowl, mu 0.6, "
-                         f"h 1/60 s, 8 k-means partitions (recomputed every 10 steps), 2-hop overlap, beta 4, "
-                         f"first {args.steps} steps from the initial drop"),
-            "n_bodies": sc.n_bodies, "partitions": int(sc.parts_per_scene[0]), "halo_k": sc.halo_k,
-            "beta": sc.beta, "sweeps": f"{args.mode}, tol {args.tol}, cap {cap}",
-            "warm_start": "learned (guarded per partition)" if "learned" in runs else "plain",
-            "interface_coupling": COUPLING_NAMES[COUPLING_FLAGS[args.coupling]],
-            "learned_vs_plain": {k: {"body_steps_per_s": v["value"], "ms_per_step": v["ms_per_step"],
-                                     "sweeps_per_step": round(v["sweeps_mean"], 2),
-                                     "partition_sweeps_per_step": round(v["sweeps_part_mean"], 2),
-                                     "unconverged_partition_steps": int(v["unconverged"]),
-                                     "steps_hitting_cap_pct": round(100.0 * v["steps_capped"] / args.steps, 2),
-                                     "exact_residual_step_after": v["exact_next"],
-                                     "exact_residual_sampled_mean": (float(np.mean(v["exact_sampled"]))
-                                                                     if v["exact_sampled"] else None),
-                                     "exact_residual_sampled_median": (float(np.median(v["exact_sampled"]))
-                                                                       if v["exact_sampled"] else None),
-                                     "exact_residual_samples": len(v["exact_sampled"])}
-                                 for k, v in runs.items()},
-            "mean_sweeps_per_step": round(sweeps_mean, 2), "unconverged_partition_steps": int(unconv),
-            "last_step": {k: last[k] for k in ("n_contacts", "n_copies", "n_replicas", "n_overlap",
-                                               "max_colours")},
-        },
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_pgs (coloured projected Gauss-Seidel, one workgroup per partition)",
-            "launches": int(pgs_launches), "ms_per_launch": pgs_ms / max(1, pgs_launches),
-            "alg_bytes_per_launch": pgs_bytes / max(1, pgs_launches),
-        },
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
-    w.close()
+    bench_tower(args)
 
 
 if __name__ == "__main__":

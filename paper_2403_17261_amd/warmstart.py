@@ -2,7 +2,9 @@
 
 1. collect(): step bowl-pile scenes (seeded 100..131) in adaptive mode with
    the feature export on and keep, every few steps, each contact copy's
-   twelve features and its final impulses divided by the impulse scale s.
+   twelve features and its final impulses divided by the impulse scale s,
+   from the partitions whose sweeps reached the tolerance (a partition stopped
+   by the sweep cap has impulses that are not the solution it should learn).
 2. fit(): Adam on the device trainer (``ovl_mlp_train_step``); PyTorch only
    holds the rows on the device and draws the shuffles.
 3. The parameters go to ``data/warmstart_mlp.npz`` with the training record.
@@ -27,22 +29,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def collect(seeds, n_bodies=4000, steps=300, start=140, every=10, tol=1e-4, cap=1000):
+def converged_rows(w, tol):
+    """Mask over the last step's training rows (contact copies in uid order):
+    True where the copy's partition stopped with its sweep residual <= tol."""
+    kind = w.debug("copy_kind")
+    pco = w.debug("part_copy_off")
+    resid = w.debug("part_resid")
+    contacts = np.nonzero(kind == 1)[0]
+    part = np.searchsorted(pco, contacts, side="right") - 1
+    return resid[part] <= tol
+
+
+def bowl(n_bodies, seed, parts=4, steps=300):
+    """A config-2-style bowl pile of n_bodies spheres (geometry scaled to the count)."""
+    from paper_2403_17261_amd import scenes
+
+    blk = scenes.bowl_scene(n_bodies, seed, parts, scale=(n_bodies / 20000.0) ** (1.0 / 3.0))
+    sc = scenes._assemble([blk], f"bowl-{n_bodies}-seed{seed}", halo_k=2, beta=4, dt=1 / 60, iters=30,
+                          steps=steps, rebalance_every=10)
+    return sc, blk["centroids"]
+
+
+def collect(seeds, n_bodies=4000, steps=300, start=140, every=10, tol=1e-4, cap=1000, converged_only=True):
     import paper_2403_17261_amd as ovl
     from paper_2403_17261_amd import scenes
 
     Xs, Ts = [], []
     for sd in seeds:
-        blk = scenes.bowl_scene(n_bodies, sd, 4, scale=(n_bodies / 20000.0) ** (1.0 / 3.0))
-        sc = scenes._assemble([blk], f"bowl-{n_bodies}-seed{sd}", halo_k=2, beta=4, dt=1 / 60, iters=30,
-                              steps=steps, rebalance_every=10)
+        sc, cent = bowl(n_bodies, sd, steps=steps)
         p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=ovl.MODE_ADAPTIVE, tol=tol, warmstart=ovl.WARM_PLAIN)
         w = ovl.World(sc, p)
         w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
         w.set_feature_export(True)
-        owner, cent = sc.owner, blk["centroids"]
+        owner = sc.owner
         t0 = time.time()
-        rows = 0
+        rows = dropped = 0
         for t in range(steps):
             if t > 0 and t % 10 == 0:
                 st = w.read_state()
@@ -52,12 +73,65 @@ def collect(seeds, n_bodies=4000, steps=300, start=140, every=10, tol=1e-4, cap=
             if t >= start and (t - start) % every == 0:
                 X, T = w.training_rows()
                 ok = np.isfinite(X).all(1) & np.isfinite(T).all(1)
+                if converged_only:
+                    conv = converged_rows(w, tol)
+                    dropped += int((ok & ~conv).sum())
+                    ok &= conv
                 Xs.append(X[ok])
                 Ts.append(T[ok])
                 rows += int(ok.sum())
         w.close()
-        log(f"seed {sd}: {rows} rows in {time.time() - t0:.1f} s")
+        log(f"seed {sd}: {rows} rows ({dropped} from unconverged partitions left out) in {time.time() - t0:.1f} s")
     return np.concatenate(Xs), np.concatenate(Ts)
+
+
+def ab_sweeps(w, params):
+    """From the world's current state and warm-start cache, one step with the
+    plain start and one with the learned start (guarded), each from the same
+    state and cache; the state and cache are restored.  Returns the partitions'
+    sweep counts and sweep residuals (plain, learned)."""
+    import paper_2403_17261_amd as ovl
+
+    s, c = w.read_state(), w.cache()
+    out = []
+    for mode in (ovl.WARM_PLAIN, ovl.WARM_LEARNED):
+        w.set_warmstart(mode, params if mode == ovl.WARM_LEARNED else None)
+        w.step(1, stats=True)
+        out.append((w.debug("part_iters").copy(), w.debug("part_resid").copy()))
+        w.write_state(s, keep_cache=False)
+        w.write_cache(c)
+    w.set_warmstart(ovl.WARM_PLAIN)
+    return out
+
+
+def evaluate(params, seeds, n_bodies=4000, steps=300, start=140, every=5, tol=1e-4, cap=1000):
+    """Sweeps to tol of the plain and the learned start on the same states: bowl
+    piles of the given seeds stepped with the plain start; every `every` steps
+    from `start` on, the next step is taken both ways from the same state and
+    cache.  Returns per-partition-step sweep counts and convergence flags."""
+    import paper_2403_17261_amd as ovl
+    from paper_2403_17261_amd import scenes
+
+    res = {"plain": [], "learned": [], "plain_conv": [], "learned_conv": []}
+    for sd in seeds:
+        sc, cent = bowl(n_bodies, sd, steps=steps)
+        p = ovl.make_params(dt=sc.dt, max_iters=cap, mode=ovl.MODE_ADAPTIVE, tol=tol, warmstart=ovl.WARM_PLAIN)
+        w = ovl.World(sc, p)
+        w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        G = int(np.sum(sc.parts_per_scene))
+        for t in range(steps):
+            if t > 0 and t % 10 == 0:
+                owner, cent = scenes.kmeans_owner(w.read_state()[:, :3], G, iters=3, centroids=cent)
+                w.set_partitions(owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+            if t >= start and (t - start) % every == 0:
+                (ip, rp), (il, rl) = ab_sweeps(w, params)
+                res["plain"] += ip.tolist()
+                res["learned"] += il.tolist()
+                res["plain_conv"] += (rp <= tol).tolist()
+                res["learned_conv"] += (rl <= tol).tolist()
+            w.step(1)
+        w.close()
+    return {k: np.array(v) for k, v in res.items()}
 
 
 def _val_loss(params, Xv, Tv):
