@@ -344,6 +344,25 @@ const char* ovl_mlp_last_error(const ovl_mlp* m);
  * (the kernel the learned warm start uses). */
 ovl_status ovl_mlp_infer(const float* params, int64_t n_params, const float* x, int64_t n, float* y);
 
+/* Gradient and loss of a batch, like ovl_mlp_gradient, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc): no trainer handle, nothing allocated, no
+ * synchronisation.  All pointers are device memory on the current device:
+ * params [OVL_MLP_PARAMS], rows x [n][12] and targets t [n][3] (read); grad
+ * [OVL_MLP_PARAMS] and loss [1] (written: the gradient of the mean squared
+ * error and that error, the same bits ovl_mlp_gradient returns for the same
+ * rows).  The work is queued on `stream` (a hipStream_t; NULL: the null
+ * stream); results are there once the stream reaches it.  The blocks' partial
+ * sums live in one fixed array per device, alive until the process ends, of
+ * room for OVL_MLP_STATIC_ROWS rows (about 1.3 MB): every call on a device uses
+ * the same array, so calls that overlap on one device (other streams, other
+ * host threads) race and must be ordered by the caller.  Errors, with nothing
+ * queued: INVALID_ARG (NULL pointer, n <= 0), CAPACITY (n above
+ * OVL_MLP_STATIC_ROWS), DEVICE; the text is ovl_mlp_last_error(NULL). */
+#define OVL_MLP_STATIC_ROWS 8192
+ovl_status ovl_mlp_gradient_static(const float* params, const float* x, const float* t, int64_t n, float* grad,
+                                   float* loss, void* stream);
+
 /* Force the sweep count of every partition of the next step (parity checks
  * of adaptive runs); iters == NULL clears it.  [G] entries, each >= 0. */
 ovl_status ovl_force_iters(ovl_world* w, const int32_t* iters, int32_t n_parts);

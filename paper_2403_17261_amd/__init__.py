@@ -132,6 +132,7 @@ def lib():
             "ovl_mlp_get_params": (C.c_int, [P, P, C.c_int64]),
             "ovl_mlp_last_error": (C.c_char_p, [P]),
             "ovl_mlp_infer": (C.c_int, [P, C.c_int64, P, C.c_int64, P]),
+            "ovl_mlp_gradient_static": (C.c_int, [P, P, P, C.c_int64, P, P, P]),
             "ovl_set_launch": (C.c_int, [P, C.POINTER(ovl_launch_cfg)]),
             "ovl_get_launch": (C.c_int, [P, C.POINTER(ovl_launch_cfg)]),
             "ovl_launch_candidates": (C.c_int32, [P, C.c_int32]),
@@ -413,6 +414,22 @@ def ovl_mlp_infer(params, x):
     if st != OK:
         raise OvlError(st, "ovl_mlp_infer")
     return Y
+
+
+MLP_STATIC_ROWS = 8192  # OVL_MLP_STATIC_ROWS
+
+
+def ovl_mlp_gradient_static(params, x, t, grad, loss, stream=None):
+    """Gradient and loss of a batch without any allocation: every argument is a
+    contiguous float32 device tensor on the current device (params [5187],
+    x [n, 12], t [n, 3], grad [5187] and loss [1] written), queued on the HIP
+    stream handle `stream` (None: the null stream)."""
+    n = int(x.shape[0])
+    st = lib().ovl_mlp_gradient_static(C.c_void_p(params.data_ptr()), C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(t.data_ptr()), n, C.c_void_p(grad.data_ptr()),
+                                       C.c_void_p(loss.data_ptr()), C.c_void_p(stream))
+    if st != OK:
+        raise OvlError(st, lib().ovl_mlp_last_error(None).decode())
 
 
 class Trainer:

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -332,6 +333,22 @@ __global__ void k_mlp_adam(float* __restrict__ params, float* __restrict__ m, fl
   params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// The mean squared error of a batch from the blocks' summed squared errors:
+// summed in block order in double and divided by the element count, the same
+// arithmetic as the host does for the trainer's gradient.
+__global__ void k_mlp_loss(const float* __restrict__ lpart, int nblk, int64_t n, float* __restrict__ loss) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double sse = 0.0;
+  for (int b = 0; b < nblk; ++b) sse += lpart[b];
+  *loss = (float)(sse / ((double)n * kMlpOut));
+}
+
+// Partial results of ovl_mlp_gradient_static: each block's gradient, then each
+// block's summed squared error.  One copy per device, alive until the process
+// ends; host code reaches it only through the address kept per device below.
+constexpr int kStaticBlocks = OVL_MLP_STATIC_ROWS / kTrRows;
+static __device__ __align__(256) float scratch[kStaticBlocks * kMlpParams + kStaticBlocks];
+
 }  // namespace
 
 hipError_t launch_mlp_world(const WP& w, hipStream_t s) {
@@ -363,6 +380,28 @@ struct ovl_mlp {
 namespace {
 
 thread_local std::string g_mlp_error;
+// the last error of ovl_mlp_gradient_static (a fixed text; nothing allocated)
+thread_local const char* g_static_error = nullptr;
+
+// Device address of `scratch`, taken once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+float* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    // the gradient kernel's LDS is above the default limit
+    if (hipFuncSetAttribute((const void*)k_mlp_grad, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(TrainLds)) != hipSuccess)
+      return nullptr;
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
 
 bool mlp_reserve(ovl_mlp* M, int64_t n) {
   const int nblk = (int)((n + kTrRows - 1) / kTrRows);
@@ -518,7 +557,50 @@ ovl_status ovl_mlp_get_params(ovl_mlp* M, float* out, int64_t n) {
   return OVL_OK;
 }
 
-const char* ovl_mlp_last_error(const ovl_mlp* M) { return M ? M->err.c_str() : g_mlp_error.c_str(); }
+const char* ovl_mlp_last_error(const ovl_mlp* M) {
+  if (M) return M->err.c_str();
+  return g_static_error ? g_static_error : g_mlp_error.c_str();
+}
+
+ovl_status ovl_mlp_gradient_static(const float* params, const float* x, const float* t, int64_t n, float* grad,
+                                   float* loss, void* stream) {
+  g_static_error = nullptr;
+  if (!params || !x || !t || !grad || !loss) {
+    g_static_error = "ovl_mlp_gradient_static: NULL pointer";
+    return OVL_ERR_INVALID_ARG;
+  }
+  if (n <= 0) {
+    g_static_error = "ovl_mlp_gradient_static: n must be positive";
+    return OVL_ERR_INVALID_ARG;
+  }
+  if (n > OVL_MLP_STATIC_ROWS) {
+    g_static_error = "ovl_mlp_gradient_static: n exceeds OVL_MLP_STATIC_ROWS (8192 rows)";
+    return OVL_ERR_CAPACITY;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    g_static_error = "ovl_mlp_gradient_static: no current device";
+    return OVL_ERR_DEVICE;
+  }
+  float* sp = scratch_on(dev);
+  if (!sp) {
+    g_static_error = "ovl_mlp_gradient_static: could not reach the device's partial-result array";
+    return OVL_ERR_DEVICE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nblk = (int)((n + kTrRows - 1) / kTrRows);
+  float* gpart = sp;
+  float* lpart = sp + (int64_t)kStaticBlocks * kMlpParams;
+  k_mlp_grad<<<nblk, kTrBS, sizeof(TrainLds), s>>>(params, x, t, (int)n, gpart, lpart);
+  k_mlp_adam<<<nblocks(kMlpParams, 256), 256, 0, s>>>(nullptr, nullptr, nullptr, gpart, nblk, grad, 0, 0.0f, 0.9f,
+                                                      0.999f, 1.0f, 1.0f, 1e-8f);
+  k_mlp_loss<<<1, 64, 0, s>>>(lpart, nblk, n, loss);
+  if (hipGetLastError() != hipSuccess) {
+    g_static_error = "ovl_mlp_gradient_static: launch failed";
+    return OVL_ERR_DEVICE;
+  }
+  return OVL_OK;
+}
 
 ovl_status ovl_mlp_infer(const float* params, int64_t n_params, const float* x, int64_t n, float* y) {
   if (!params || n_params != kMlpParams || (n > 0 && (!x || !y)) || n < 0 || n > (1 << 26))
