@@ -240,7 +240,9 @@ hipError_t launch_graph(const WP& w, int32_t* scan_scratch, hipStream_t s);
 hipError_t launch_solve_pre(const WP& w, hipStream_t s);
 hipError_t launch_pgs(const WP& w, hipStream_t s, hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 hipError_t launch_solve_post(const WP& w, hipStream_t s, bool exact_residual);
-hipError_t pgs_occupancy(int cfg, bool caps, int* per_cu_lds, int* per_cu_glob);
+// resident solver workgroups per compute unit (LDS and global-memory variants)
+// of launch configuration cfg, for the variant a world with (caps, split) runs
+hipError_t pgs_occupancy(int cfg, bool caps, bool split, int* per_cu_lds, int* per_cu_glob);
 hipError_t launch_reset_lambda(const WP& w, hipStream_t s);
 hipError_t launch_digest(const WP& w, unsigned long long* out, hipStream_t s);
 

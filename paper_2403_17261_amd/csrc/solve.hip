@@ -1792,18 +1792,22 @@ hipError_t set_attrs_t() {
   return e;
 }
 
-template <int BS, int R>
-hipError_t occupancy_t(bool caps, int* per_cu_lds, int* per_cu_glob) {
+// resident workgroups per compute unit of the variants launch_pgs_t runs
+template <int BS, int R, bool kCaps, bool kSplit>
+hipError_t occupancy_v(int* per_cu_lds, int* per_cu_glob) {
   const size_t lds = 2 * ((size_t)R + 1) * sizeof(float4);
   hipError_t e;
-  if (caps) {
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, true, false>, BS, lds)))
-      return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, true, false>, BS, 0);
-  }
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, false, false>, BS, lds)))
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_lds, k_pgs<BS, R, true, kCaps, kSplit>, BS, lds)))
     return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, false, false>, BS, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_glob, k_pgs<BS, R, false, kCaps, kSplit>, BS, 0);
+}
+
+template <int BS, int R>
+hipError_t occupancy_t(bool caps, bool split, int* per_cu_lds, int* per_cu_glob) {
+  if (caps) return split ? occupancy_v<BS, R, true, true>(per_cu_lds, per_cu_glob)
+                         : occupancy_v<BS, R, true, false>(per_cu_lds, per_cu_glob);
+  return split ? occupancy_v<BS, R, false, true>(per_cu_lds, per_cu_glob)
+               : occupancy_v<BS, R, false, false>(per_cu_lds, per_cu_glob);
 }
 
 template <int BS, int R>
@@ -1845,12 +1849,12 @@ hipError_t pgs_set_attributes() {
   return set_attrs_t<256, 2400>();
 }
 
-hipError_t pgs_occupancy(int cfg, bool caps, int* per_cu_lds, int* per_cu_glob) {
+hipError_t pgs_occupancy(int cfg, bool caps, bool split, int* per_cu_lds, int* per_cu_glob) {
   switch (cfg) {
-    case 0: return occupancy_t<1024, 4800>(caps, per_cu_lds, per_cu_glob);
-    case 1: return occupancy_t<512, 2400>(caps, per_cu_lds, per_cu_glob);
-    case 2: return occupancy_t<256, 1200>(caps, per_cu_lds, per_cu_glob);
-    case 3: return occupancy_t<256, 2400>(caps, per_cu_lds, per_cu_glob);
+    case 0: return occupancy_t<1024, 4800>(caps, split, per_cu_lds, per_cu_glob);
+    case 1: return occupancy_t<512, 2400>(caps, split, per_cu_lds, per_cu_glob);
+    case 2: return occupancy_t<256, 1200>(caps, split, per_cu_lds, per_cu_glob);
+    case 3: return occupancy_t<256, 2400>(caps, split, per_cu_lds, per_cu_glob);
   }
   return hipErrorInvalidValue;
 }

@@ -315,7 +315,7 @@ struct ovl_world {
   // apply a launch configuration (validated by the caller)
   bool apply_launch(const ovl_launch_cfg& c, int cfg) {
     int per_lds = 0, per_glob = 0;
-    if (pgs_occupancy(cfg, wp.has_caps != 0, &per_lds, &per_glob) != hipSuccess) return false;
+    if (pgs_occupancy(cfg, wp.has_caps != 0, wp.msplit != 0, &per_lds, &per_glob) != hipSuccess) return false;
     launch = c;
     wp.pgs_cfg = cfg;
     wp.pgs_persistent = c.persistent ? 1 : 0;
@@ -713,6 +713,8 @@ ovl_status ovl_set_params(ovl_world* w, const ovl_params* params) {
   std::string e;
   if (validate_params(params, e) != OVL_OK) return w->fail(OVL_ERR_INVALID_ARG, e);
   w->set_params(*params);
+  // mass splitting runs other solver variants: size the persistent grid for them
+  if (!w->apply_launch(w->launch, w->wp.pgs_cfg)) return w->fail(OVL_ERR_DEVICE, "occupancy query failed");
   return OVL_OK;
 }
 
