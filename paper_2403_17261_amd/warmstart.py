@@ -9,7 +9,10 @@
    holds the rows on the device and draws the shuffles.
 3. The parameters go to ``data/warmstart_mlp.npz`` with the training record.
 
-    python -m paper_2403_17261_amd.warmstart [--seeds 100-131] [--bodies 4000]
+    python -m paper_2403_17261_amd.warmstart [--seeds 100-131] [--bodies 4000] [--tol 1e-2]
+
+4. The record also holds the sweeps to tolerance of the plain and the learned
+   start from the same states of held-out bowls (evaluate()).
 """
 from __future__ import annotations
 
@@ -176,29 +179,45 @@ def main():
     ap.add_argument("--seeds", default="100-131")
     ap.add_argument("--val", type=int, default=4, help="the last this many seeds are held out")
     ap.add_argument("--bodies", type=int, default=4000)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--tol", type=float, default=1e-2,
+                    help="sweep tolerance of the collection runs; rows come only from partitions that reach it")
+    ap.add_argument("--eval-seeds", default="140-143", help="held-out bowls for the sweep comparison")
     ap.add_argument("--out", default=WEIGHTS)
     args = ap.parse_args()
     a, b = (int(x) for x in args.seeds.split("-"))
     seeds = list(range(a, b + 1))
     tr_seeds, va_seeds = seeds[:-args.val], seeds[-args.val:]
+    a, b = (int(x) for x in args.eval_seeds.split("-"))
+    ev_seeds = list(range(a, b + 1))
     t0 = time.time()
-    X, T = collect(tr_seeds, args.bodies)
-    Xv, Tv = collect(va_seeds, args.bodies)
+    X, T = collect(tr_seeds, args.bodies, tol=args.tol)
+    Xv, Tv = collect(va_seeds, args.bodies, tol=args.tol)
     log(f"collected {len(X)} training and {len(Xv)} validation rows in {time.time() - t0:.0f} s")
     # baseline: predicting the plain start (lambda_n from the previous step, no friction)
     base = np.zeros_like(Tv)
     base[:, 0] = Xv[:, 9]
     base_loss = float(((base - Tv) ** 2).mean())
     params, hist = fit(X, T, Xv, Tv, epochs=args.epochs)
-    rec = {"train_seeds": tr_seeds, "val_seeds": va_seeds, "bodies": args.bodies, "rows": int(len(X)),
+    # what the network changes: sweeps to the tolerance from the same states, plain against learned
+    sweeps = {}
+    for tol in sorted({args.tol, 3e-3}, reverse=True):
+        r = evaluate(params, ev_seeds, n_bodies=args.bodies, every=10, tol=tol)
+        sweeps[f"{tol:g}"] = {"partition_steps": int(len(r["plain"])),
+                              "plain_mean_sweeps": float(r["plain"].mean()),
+                              "learned_mean_sweeps": float(r["learned"].mean()),
+                              "plain_converged": float(r["plain_conv"].mean()),
+                              "learned_converged": float(r["learned_conv"].mean())}
+        log(f"held-out sweeps at {tol:g}: {json.dumps(sweeps[f'{tol:g}'])}")
+    rec = {"train_seeds": tr_seeds, "val_seeds": va_seeds, "eval_seeds": ev_seeds, "bodies": args.bodies,
+           "collection_tol": args.tol, "converged_rows_only": True, "rows": int(len(X)),
            "val_rows": int(len(Xv)), "history": hist, "val_loss_plain_start": base_loss,
-           "seconds": time.time() - t0}
+           "held_out_sweeps": sweeps, "seconds": time.time() - t0}
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.savez(args.out, params=params.astype(np.float32), record=json.dumps(rec))
     log(json.dumps(rec))
     print(json.dumps({"weights": args.out, **{k: rec[k] for k in ("rows", "val_rows", "val_loss_plain_start")},
-                      "val_loss": hist[-1]["val_loss"]}))
+                      "val_loss": hist[-1]["val_loss"], "held_out_sweeps": sweeps}))
 
 
 def load(path=WEIGHTS):
