@@ -16,6 +16,12 @@ constexpr int kColStride = kMaxColours + 1;
 constexpr int kPgsCfgCount = 4;
 constexpr int kPgsCfgBlock[kPgsCfgCount] = {1024, 512, 256, 256};
 constexpr int kPgsCfgReps[kPgsCfgCount] = {4800, 2400, 1200, 2400};
+// the sweeps' record loads may run up to one workgroup past a partition's last
+// slot (lanes past a colour's end), so the record arrays carry this many spare slots
+constexpr int kSlotPad = 1024;
+static_assert(kSlotPad >= kPgsCfgBlock[0] && kSlotPad >= kPgsCfgBlock[1] && kSlotPad >= kPgsCfgBlock[2] &&
+                  kSlotPad >= kPgsCfgBlock[3],
+              "the record arrays must be padded by the largest solver workgroup");
 constexpr int kBlock = 256;          // generic per-item kernels
 constexpr int kKeep = 16;            // contact keys per body kept between the two narrow-phase passes
 constexpr int kLbLdsCap = 12288;     // load balancing: scenes up to this many bodies keep their sets in LDS

@@ -877,14 +877,19 @@ __device__ __forceinline__ Slots slots_of(const WP& w, int s0) {
   return S;
 }
 
-// fetch_rec for the slot at local index l of the partition (see fetch_rec)
+// fetch_rec for the slot at local index base + tid of the partition (see
+// fetch_rec): `base` is the same in every lane, so its byte offset joins the
+// scalar bases, and toff = 16 tid is the lane's vector offset.  Lanes may read
+// up to a workgroup past the last slot: the record arrays are padded by
+// kSlotPad slots.
 template <bool kCaps>
-__device__ __forceinline__ void fetch_local(const Slots& S, uint32_t l, Rec& R, bool packed) {
-  const uint32_t o = l << 4;
+__device__ __forceinline__ void fetch_lane(const Slots& S, int base, uint32_t toff, Rec& R, bool packed) {
+  // one 32-bit vector offset from the partition's scalar bases for all the loads
+  const uint32_t o = ((uint32_t)base << 4) + toff;
   R.r0 = *reinterpret_cast<const float4*>(S.r0 + o);
   R.r1 = *reinterpret_cast<const float4*>(S.r1 + o);
   R.r2 = *reinterpret_cast<const float4*>(S.r2 + o);
-  if (!packed) R.id = *reinterpret_cast<const int2*>(S.ids + (l << 3));
+  if (!packed) R.id = *reinterpret_cast<const int2*>(S.ids + (o >> 1));
   R.lam = *reinterpret_cast<const float4*>(S.lam + o);
   if (kCaps) {
     R.g0 = *reinterpret_cast<const float4*>(S.g0 + o);
@@ -1088,7 +1093,7 @@ __device__ float4 g_zero_body[2];
 // arithmetic is the same in both and no lane branches on it before the store.
 // A zero body stays zero in LDS because a zero inverse mass adds only zeros.
 template <bool solve, bool kCaps = false, bool kSweep = false, bool kLds = false>
-__device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, float4* lam_out, int r0 = 0) {
+__device__ __forceinline__ float4 do_slot(const WP& w, Vel V, Rec& R, float& rl, int r0 = 0) {
   Bod A = ld_body(V, R.ia);
   Bod B;
   const bool hasB = R.ib >= 0;
@@ -1104,21 +1109,30 @@ __device__ __forceinline__ void do_slot(const WP& w, Vel V, Rec& R, float& rl, f
   } else {
     B = {mk(0, 0, 0), mk(0, 0, 0), 0.0f, 0.0f};
   }
+  // The record's registers are only read (the new impulses go to L): a record
+  // loaded one colour ahead then stays in the registers it was loaded into.
+  float4 L = R.lam;
   if (kCaps && R.gen) {
     const float4 axA = w.rep_ax[r0 + R.ia];
     const float4 axB = hasB ? w.rep_ax[r0 + R.ib] : float4{};
     if (R.joint)
-      joint_rows<solve, true>(R, A, B, w.cfm, R.lam, rl, axA, axB);
+      joint_rows<solve, true>(R, A, B, w.cfm, L, rl, axA, axB);
     else
-      gen_contact_rows<solve>(R, A, B, w.cfm, R.lam, rl, axA, axB);
+      gen_contact_rows<solve>(R, A, B, w.cfm, L, rl, axA, axB);
   } else if (R.joint) {
-    joint_rows<solve>(R, A, B, w.cfm, R.lam, rl);
+    joint_rows<solve>(R, A, B, w.cfm, L, rl);
   } else {
-    contact_rows<solve>(R, A, B, w.cfm, R.lam, rl);
+    contact_rows<solve>(R, A, B, w.cfm, L, rl);
   }
   st_body(V, R.ia, A);
   if ((kSweep && kLds) || hasB) st_body(V, R.ib, B);
-  if (solve) *lam_out = R.lam;
+  return L;
+}
+
+// a sweep never changes the fourth component of an impulse (the packed ids):
+// only x, y, z are stored
+__device__ __forceinline__ void store_lam(char* p, float4 L) {
+  *reinterpret_cast<float3*>(p) = make_float3(L.x, L.y, L.z);
 }
 
 // s_waitcnt operand (gfx9 encoding) that waits for every vector-memory access
@@ -1231,7 +1245,7 @@ __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int*
       Rec R;
       load_rec<kCaps>(w, slot, R, packed);
       if (learned && !R.joint) R.lam = w.r_lamL[slot];
-      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, unused, nullptr, r0);
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, unused, r0);
     }
     vel_sync<kLds>();
   }
@@ -1255,35 +1269,60 @@ __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int*
 // colour's slot at its own index (its record `cur`, loaded one colour ahead)
 // and, in colours larger than the workgroup, the slots BS, 2 BS, ... further
 // on; meanwhile the first slot of the next colour (local range [n0, n1), never
-// empty) is loaded into `nxt`.  Every lane issues that load, lanes past the
-// colour's end at its last slot, so each wave issues the same loads in every
-// pass and the wait for `cur` can leave the new loads in flight.  Ends with the
-// workgroup barrier between colours.
+// empty) is loaded into `nxt`.  Every lane issues that load (lanes past the
+// colour's end read slots after it, which they never use), so each wave issues
+// the same loads in every pass and the wait for `cur` can leave the new loads
+// in flight.  All record addresses are a scalar base plus the lane's offset
+// toff = 16 tid.  Ends with the workgroup barrier between colours.
 template <int BS, bool kCaps, bool kLds>
 __device__ __forceinline__ void colour_pass(const WP& w, Vel V, const Slots& S, int b0, int b1, int n0, int n1,
                                             bool prefetch, Rec& cur, bool& has_cur, Rec& nxt, bool& has_nxt,
-                                            int first, float& rl, int r0, bool packed) {
+                                            int first, float& rl, int r0, bool packed, uint32_t toff,
+                                            int* over = nullptr, float tol = 0.0f) {
   const int tid = threadIdx.x;
   has_nxt = prefetch && n0 + tid < n1;
-  fetch_local<kCaps>(S, (uint32_t)min(n0 + tid, n1 - 1), nxt, packed);
-  if (has_cur) {
-    const uint32_t l = (uint32_t)(b0 + tid);
-    decode<kCaps>(cur, packed);
-    do_slot<true, kCaps, true, kLds>(w, V, cur, rl, reinterpret_cast<float4*>(S.lam + (l << 4)), r0);
+  fetch_lane<kCaps>(S, n0, toff, nxt, packed);
+  // the thread's second slot of a colour larger than the workgroup: loaded once
+  // the first one is decoded, so that its loads run during the first one's rows
+  const int k2 = b0 + first;
+  const bool has2 = tid < b1 - k2;
+  // Wait here for `cur` (loaded one colour ahead, before the loads just issued
+  // for `nxt`), ahead of the second slot's loads: a wait placed after those
+  // would also hold back the prefetch.  (With separate record ids, 5 or 7
+  // loads per record, this waits for one prefetch load too.)
+  constexpr int kFetchLoads = kCaps ? 6 : 4;
+  __builtin_amdgcn_s_waitcnt(kWaitVmem0 | kFetchLoads);
+  decode<kCaps>(cur, packed);
+  Rec R2;
+  if (has2) fetch_lane<kCaps>(S, k2, toff, R2, packed);
+  // both slots' impulses are stored after both are solved, so that the wait for
+  // the second slot's loads does not also wait for the first slot's store
+  float4 Lc, L2;
+  if (has_cur) Lc = do_slot<true, kCaps, true, kLds>(w, V, cur, rl, r0);
+  if (has2) {
+    decode<kCaps>(R2, packed);
+    L2 = do_slot<true, kCaps, true, kLds>(w, V, R2, rl, r0);
   }
-  for (int l = b0 + tid + first; l < b1; l += BS) {
-    Rec R;
-    fetch_local<kCaps>(S, (uint32_t)l, R, packed);
-    decode<kCaps>(R, packed);
-    do_slot<true, kCaps, true, kLds>(w, V, R, rl, reinterpret_cast<float4*>(S.lam + ((uint32_t)l << 4)), r0);
+  if (has_cur) store_lam(S.lam + (((uint32_t)b0 << 4) + toff), Lc);
+  if (has2) store_lam(S.lam + (((uint32_t)k2 << 4) + toff), L2);
+  for (int k = k2 + BS; k < b1; k += BS) {
+    if (tid < b1 - k) {
+      Rec R;
+      fetch_lane<kCaps>(S, k, toff, R, packed);
+      decode<kCaps>(R, packed);
+      store_lam(S.lam + (((uint32_t)k << 4) + toff), do_slot<true, kCaps, true, kLds>(w, V, R, rl, r0));
+    }
   }
+  // the last colour of an adaptive sweep: a wave with a residual above the
+  // tolerance marks the sweep (read after the barrier)
+  if (over != nullptr && __ballot(rl > tol) != 0 && lane_id() == 0) *over = 1;
   vel_sync<kLds>();
 }
 
 // Solve one partition with a workgroup of BS threads.  V holds its replica
 // velocities (LDS, or its slice of rep_v4 for the global variant).
 template <int BS, bool kCaps, bool kSplit, bool kLds>
-__device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red) {
+__device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red, int* over) {
   const int tid = threadIdx.x;
   const int N = w.N;
   const int r0 = w.part_rep_off[p];
@@ -1292,6 +1331,7 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   const int ncol = w.part_ncol[p];
   const bool packed = nr < kPackReps;  // uniform: ids from the impulses' fourth component
   if (tid < kColStride) coff[tid] = w.part_col_off[p * kColStride + tid];
+  if (tid < 3) over[tid] = 0;
   if (kLds && tid == 0) {
     // the zero body at index -1 (a static second body in the sweeps)
     V.p[-1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -1327,7 +1367,7 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
     for (int slot = s0 + coff[c] + tid; slot < e; slot += BS) {
       Rec R;
       load_rec<kCaps>(w, slot, R, packed);
-      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, rl, nullptr, r0);
+      if (R.lam.x != 0.0f || R.lam.y != 0.0f || R.lam.z != 0.0f) do_slot<false, kCaps>(w, V, R, rl, r0);
     }
     vel_sync<kLds>();
   }
@@ -1339,16 +1379,17 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   // its impulses are stored: then nothing is prefetched and every slot is
   // loaded where it is solved.
   const int first = ncol == 1 ? 0 : BS;
-  // colour offsets in two registers (lane k holds coff[k]); read with readlane
+  // colour offsets: lane k of cv0 holds coff[k], cv1 the last one; read with readlane
   const int cv0 = coff[lane_id()];
-  const int cv1 = coff[kColStride - 1];
+  const int cv1 = __builtin_amdgcn_readfirstlane(coff[kColStride - 1]);
   auto co = [&](int k) { return k < 64 ? __builtin_amdgcn_readlane(cv0, k) : cv1; };
   const Slots S = slots_of(w, s0);
   // two record sets used in turn: one is solved while the next colour's first
   // slot is loaded into the other, so no record is ever copied between them
   Rec ra, rb;
   bool ha = ncol > 1 && co(0) + tid < co(1), hb = false;
-  if (ncol > 0) fetch_local<kCaps>(S, (uint32_t)min(co(0) + tid, co(1) - 1), ra, packed);
+  const uint32_t toff = (uint32_t)tid << 4;
+  if (ncol > 0) fetch_lane<kCaps>(S, co(0), toff, ra, packed);
   // Nothing may still be in flight into the first set when the loop is entered:
   // otherwise the wait placed before its first use would also hold back the
   // next colour's prefetch in every pass.
@@ -1359,26 +1400,48 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   } else if (cap > 0) {
     int c = 0;
     rl = 0.0f;
-    // after colour c: the end of a sweep takes the residual and may stop
+    // Adaptive sweeps stop once no slot's residual exceeds the tolerance: the
+    // last colour of sweep s marks over[s mod 3] if one does (three flags in
+    // turn, so that clearing the flag of sweep s + 2 after sweep s never races
+    // with a read or a mark).  The residual itself is reduced once, at the end.
+    const bool check = !w.forced && w.adaptive;
+    int k3 = 0;
+    // after colour c: the end of a sweep may stop
     auto next_colour = [&]() {
       if (++c < ncol) return false;
       c = 0;
-      rho = block_max<BS>(rl, red);
-      rl = 0.0f;
       ++it;
-      return it >= cap || (!w.forced && w.adaptive && rho <= w.tol);
+      bool stop = it >= cap;
+      if (check) {
+        stop = stop || over[k3] == 0;
+        if (tid == 0) over[k3 == 0 ? 2 : k3 - 1] = 0;
+        k3 = k3 == 2 ? 0 : k3 + 1;
+      }
+      if (stop) rho = block_max<BS>(rl, red);
+      rl = 0.0f;
+      return stop;
     };
+    // [b0, b1): the current colour's slots, carried from the previous pass, so
+    // that a pass reads one new offset
+    const int co0 = co(0);
+    int b0 = co0, b1 = co(1);
     for (;;) {
       {
         const int cn = c + 1 < ncol ? c + 1 : 0;
-        colour_pass<BS, kCaps, kLds>(w, V, S, co(c), co(c + 1), co(cn), co(cn + 1), ncol > 1, ra, ha, rb, hb,
-                                     first, rl, r0, packed);
+        const int n0 = cn == 0 ? co0 : b1, n1 = co(cn + 1);
+        colour_pass<BS, kCaps, kLds>(w, V, S, b0, b1, n0, n1, ncol > 1, ra, ha, rb, hb, first, rl, r0, packed,
+                                     toff, check && c == ncol - 1 ? over + k3 : nullptr, w.tol);
+        b0 = n0;
+        b1 = n1;
       }
       if (next_colour()) break;
       {
         const int cn = c + 1 < ncol ? c + 1 : 0;
-        colour_pass<BS, kCaps, kLds>(w, V, S, co(c), co(c + 1), co(cn), co(cn + 1), ncol > 1, rb, hb, ra, ha,
-                                     first, rl, r0, packed);
+        const int n0 = cn == 0 ? co0 : b1, n1 = co(cn + 1);
+        colour_pass<BS, kCaps, kLds>(w, V, S, b0, b1, n0, n1, ncol > 1, rb, hb, ra, ha, first, rl, r0, packed,
+                                     toff, check && c == ncol - 1 ? over + k3 : nullptr, w.tol);
+        b0 = n0;
+        b1 = n1;
       }
       if (next_colour()) break;
     }
@@ -1429,6 +1492,7 @@ __global__ __launch_bounds__(BS) void k_pgs(WP w) {
   extern __shared__ float4 sm4[];
   __shared__ int coff[kColStride];
   __shared__ float red[BS / 64];
+  __shared__ int over[3];
   __shared__ int failed_s, item_s;
   const int tid = threadIdx.x;
   // one read of the failure flag per workgroup, so the early exit is uniform
@@ -1456,7 +1520,7 @@ __global__ __launch_bounds__(BS) void k_pgs(WP w) {
       // LDS: [0][v, 1/m of kReps replicas][0][w, 1/I of kReps replicas], indexed from the
       // first replica, so index -1 of either array is a zero entry
       const Vel V = kLds ? Vel{sm4 + 1, kReps + 1} : Vel{w.rep_v4 + w.part_rep_off[p], w.Rcap};
-      solve_partition<BS, kCaps, kSplit, kLds>(w, p, V, coff, red);
+      solve_partition<BS, kCaps, kSplit, kLds>(w, p, V, coff, red, over);
     }
     if (!w.pgs_persistent) break;
   }

@@ -156,12 +156,12 @@ struct ovl_world {
     w.cp_colour = alloc<int32_t>(g, Mcap, ok);
     w.cp_slot = alloc<int32_t>(g, Mcap, ok);
     w.cp_inv = alloc<int32_t>(g, Mcap, ok);
-    w.r_rec = alloc<float4>(g, (size_t)3 * Mcap, ok);
-    w.r_gen = alloc<float4>(g, w.has_caps ? (size_t)2 * Mcap : 1, ok);
+    w.r_rec = alloc<float4>(g, (size_t)3 * Mcap + kSlotPad, ok);
+    w.r_gen = alloc<float4>(g, w.has_caps ? (size_t)2 * Mcap + kSlotPad : 1, ok);
     w.rep_ax = alloc<float4>(g, w.has_caps ? (size_t)Rcap : 1, ok);
     w.rep_cpl = alloc<float4>(g, (size_t)2 * Rcap, ok);
-    w.r_ids = alloc<int2>(g, Mcap, ok);
-    w.r_lam = alloc<float4>(g, Mcap, ok);
+    w.r_ids = alloc<int2>(g, (size_t)Mcap + kSlotPad, ok);
+    w.r_lam = alloc<float4>(g, (size_t)Mcap + kSlotPad, ok);
     w.r_lam0 = alloc<float4>(g, Mcap, ok);
     w.rep_v4 = alloc<float4>(g, (size_t)2 * Rcap, ok);
     w.r_feat = alloc<float>(g, (size_t)kFeatStride * Mcap, ok);
