@@ -198,3 +198,37 @@ def test_trained_network_sweeps_to_tolerance_on_held_out_bowls():
     assert len(p) >= 48
     assert r["learned_conv"].mean() >= r["plain_conv"].mean() - 0.05
     assert l.mean() <= 1.05 * p.mean()
+
+
+def test_trained_network_saves_sweeps_on_a_collapsing_tower():
+    """Sweeps to tolerance, plain start against the committed network (guarded),
+    on a scene family the network never saw in training (it was trained on bowl
+    piles only): the first 16 steps of a 25x25x40 sub-tower collapse (16 column
+    partitions of the benchmark tower's partition size), each step taken both
+    ways from the same state and cache.  At the loose tolerance 1e-1 the learned
+    start needs fewer sweeps (0.85 of the plain start's when this test was
+    written), and at 3e-2 no more; both starts converge everywhere."""
+    from paper_2403_17261_amd import warmstart
+
+    params, rec = warmstart.load()
+    for tol, bound in ((1e-1, 0.95), (3e-2, 1.0)):
+        sc = scenes.config5(0, nx=25, ny=25, nz=40, cols=4)
+        p = ovl.make_params(dt=sc.dt, max_iters=1000, mode=ovl.MODE_ADAPTIVE, tol=tol, warmstart=ovl.WARM_PLAIN)
+        w = ovl.World(sc, p)
+        w.set_partitions(sc.owner, sc.parts_per_scene, halo_k=sc.halo_k, beta=sc.beta)
+        P, L, PC, LC = [], [], [], []
+        for t in range(16):
+            if t >= 1:
+                (ip, rp), (il, rl) = warmstart.ab_sweeps(w, params)
+                P += ip.tolist()
+                L += il.tolist()
+                PC += (rp <= tol).tolist()
+                LC += (rl <= tol).tolist()
+            w.step(1)
+        w.close()
+        P, L = np.array(P), np.array(L)
+        log(f"  sweeps to {tol:g} on a 25k-sphere tower: plain {P.mean():.1f}, learned {L.mean():.1f} over {len(P)} "
+            f"partition-steps (learned fewer in {np.mean(L < P):.0%}, more in {np.mean(L > P):.0%})")
+        assert len(P) == 15 * 16
+        assert np.all(PC) and np.all(LC)
+        assert L.mean() <= bound * P.mean()
