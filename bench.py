@@ -801,7 +801,7 @@ def main():
     ap.add_argument("--mode", choices=["adaptive", "fixed"], default="adaptive")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cap", type=int, default=1000)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-ladder", action="store_true", help="tower/bowl: time only the head tolerance")
     ap.add_argument("--no-configs", action="store_true", help="tower/bowl: leave out the other configurations")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -147,6 +147,22 @@ __device__ __forceinline__ bool prio_gt(uint32_t ha, int ua, uint32_t hb, int ub
 
 // ------------------------------------------------------------ colouring ----
 
+// f(l) for the local copy indices inc[k0 .. k1) of an incidence list in LDS,
+// four entries read at a time so that their loads (and f's own reads) overlap
+// instead of forming one dependent chain per neighbour.
+template <class F>
+__device__ __forceinline__ void for_incident(const uint16_t* inc, int k0, int k1, F f) {
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    const int l0 = inc[k], l1 = inc[k + 1], l2 = inc[k + 2], l3 = inc[k + 3];
+    f(l0);
+    f(l1);
+    f(l2);
+    f(l3);
+  }
+  for (; k < k1; ++k) f(inc[k]);
+}
+
 constexpr int kColBS = 1024;
 constexpr int kColLds = 16384;  // partitions with at most this many copies colour in LDS (7 B per copy)
 constexpr int kColRepLds = 8192;  // ... and at most this many replicas (incidence offsets in LDS)
@@ -298,11 +314,10 @@ __global__ __launch_bounds__(BS) void k_colour(WP w, int split) {
       const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
       for (int e = 0; e < 2; ++e) {
         if (ends[e] < 0) continue;
-        const int k1 = ioff_l[ends[e] + 1];
-        for (int k = ioff_l[ends[e]]; k < k1; ++k) {
-          const int o = u0 + inc_l[k];
+        for_incident(inc_l, ioff_l[ends[e]], ioff_l[ends[e] + 1], [&](int l) {
+          const int o = u0 + l;
           if (o != u && prio_gt(fmix32((uint32_t)o ^ w.seed), o, hu, u)) ++n;
-        }
+        });
       }
       atomicAdd(&wait_lds[(u - u0) >> 1], (uint32_t)n << (16 * ((u - u0) & 1)));
     }
@@ -324,11 +339,10 @@ __global__ __launch_bounds__(BS) void k_colour(WP w, int split) {
         const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
         for (int e = 0; e < 2; ++e) {
           if (ends[e] < 0) continue;
-          const int k1 = ioff_l[ends[e] + 1];
-          for (int k = ioff_l[ends[e]]; k < k1; ++k) {
-            const int co = col_lds[inc_l[k]];
+          for_incident(inc_l, ioff_l[ends[e]], ioff_l[ends[e] + 1], [&](int l) {
+            const int co = col_lds[l];
             if (co >= 0) used |= 1ull << co;
-          }
+          });
         }
         col_lds[u - u0] = (signed char)pick(used);
         now |= 1u << j;
@@ -342,12 +356,11 @@ __global__ __launch_bounds__(BS) void k_colour(WP w, int split) {
         const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
         for (int e = 0; e < 2; ++e) {
           if (ends[e] < 0) continue;
-          const int k1 = ioff_l[ends[e] + 1];
-          for (int k = ioff_l[ends[e]]; k < k1; ++k) {
-            const int o = u0 + inc_l[k];
+          for_incident(inc_l, ioff_l[ends[e]], ioff_l[ends[e] + 1], [&](int l) {
+            const int o = u0 + l;
             if (o != u && prio_gt(hu, u, fmix32((uint32_t)o ^ w.seed), o))
               atomicSub(&wait_lds[(o - u0) >> 1], 1u << (16 * ((o - u0) & 1)));
-          }
+          });
         }
       }
       if (!__syncthreads_or(todo != 0)) break;
