@@ -7,9 +7,10 @@
 //    the block's gradient; k_mlp_adam sums the block gradients in a fixed
 //    order and applies Adam.  No floating-point atomics.
 //  * Inference (BF16 matrix cores, FP32 accumulation): one wave evaluates 16
-//    contacts with v_mfma_f32_16x16x16_bf16 tiles; activations pass through
-//    LDS between layers (bfloat16).  The world-side kernel writes the
-//    projected prediction into the learned-start slot of every contact copy.
+//    contacts with v_mfma_f32_16x16x16_bf16 tiles, the weights held in its
+//    registers; activations pass through the wave's LDS between layers
+//    (bfloat16).  The world-side kernel writes the projected prediction into
+//    the learned-start slot of every contact copy.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -63,70 +64,103 @@ namespace {
 
 constexpr int kInfBS = 256;  // 4 waves, 16 rows each
 
-// Evaluate 16 rows held in LDS (x: [16][16] bfloat16, zero-padded) with the
-// packed network; y gets [16][3] floats.  One wave; h1/h2 are [16][64] scratch.
 // Operand layout of the 16x16x16 bf16 instruction: lane l holds A[l%16][4(l/16)+j],
 // B[4(l/16)+j][l%16] and D[4(l/16)+j][l%16], j = 0..3.
-__device__ void mlp_tile(const uint16_t* __restrict__ wb, const float* __restrict__ bias, const uint16_t* x,
-                         uint16_t* h1, uint16_t* h2, float* y) {
+//
+// A lane's share of the packed network as matrix-core operands: its B
+// fragments of the three layers and the biases of its output columns, read
+// once and kept in registers for every tile the wave evaluates.
+struct MlpLane {
+  bf16x4 w1[4], w2[4][4], w3[4];
+  float b1[4], b2[4], b3;
+};
+
+__device__ __forceinline__ void mlp_lane_load(MlpLane& n, const uint16_t* wb, const float* bias) {
+  const int l = lane_id();
+  const int row = l & 15, q = l >> 4;
+  for (int t = 0; t < 4; ++t) {
+    for (int j = 0; j < 4; ++j) n.w1[t][j] = (short)wb[(4 * q + j) * 64 + 16 * t + row];
+    n.b1[t] = bias[16 * t + row];
+    n.b2[t] = bias[64 + 16 * t + row];
+  }
+  for (int ks = 0; ks < 4; ++ks)
+    for (int t = 0; t < 4; ++t)
+      for (int j = 0; j < 4; ++j) n.w2[ks][t][j] = (short)wb[1024 + (16 * ks + 4 * q + j) * 64 + 16 * t + row];
+  for (int ks = 0; ks < 4; ++ks)
+    for (int j = 0; j < 4; ++j) n.w3[ks][j] = (short)wb[1024 + 4096 + (16 * ks + 4 * q + j) * 16 + row];
+  n.b3 = bias[128 + row];
+}
+
+// the LDS written by this wave is complete and visible to its other lanes
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Evaluate 16 rows with the network in registers.  `a` is the lane's A
+// operand of the first layer: row l%16, features 4(l/16) .. +3 as bfloat16
+// (zero-padded to 16).  h1, h2 ([16][64] bfloat16) and y ([16][4] float, the
+// three outputs of each row) are this wave's LDS.  Only the wave takes part.
+__device__ void mlp_rows(const MlpLane& n, bf16x4 a, uint16_t* h1, uint16_t* h2, float* y) {
   const int l = lane_id();
   const int row = l & 15, q = l >> 4;
   // layer 1: [16 x 16] x [16 x 64]
-  bf16x4 a;
-  for (int j = 0; j < 4; ++j) a[j] = (short)x[row * 16 + 4 * q + j];
   for (int t = 0; t < 4; ++t) {
-    bf16x4 b;
-    for (int j = 0; j < 4; ++j) b[j] = (short)wb[(4 * q + j) * 64 + 16 * t + row];
     f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, n.w1[t], c, 0, 0, 0);
     const int col = 16 * t + row;
-    for (int j = 0; j < 4; ++j) h1[(4 * q + j) * 64 + col] = to_bf16(fmaxf(c[j] + bias[col], 0.0f));
+    for (int j = 0; j < 4; ++j) h1[(4 * q + j) * 64 + col] = to_bf16(fmaxf(c[j] + n.b1[t], 0.0f));
   }
-  __syncthreads();
+  wave_lds_sync();
   // layer 2: [16 x 64] x [64 x 64]
   f32x4 acc[4];
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int ks = 0; ks < 4; ++ks) {
     bf16x4 a2;
     for (int j = 0; j < 4; ++j) a2[j] = (short)h1[row * 64 + 16 * ks + 4 * q + j];
-    for (int t = 0; t < 4; ++t) {
-      bf16x4 b;
-      for (int j = 0; j < 4; ++j) b[j] = (short)wb[1024 + (16 * ks + 4 * q + j) * 64 + 16 * t + row];
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b, acc[t], 0, 0, 0);
-    }
+    for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, n.w2[ks][t], acc[t], 0, 0, 0);
   }
   for (int t = 0; t < 4; ++t) {
     const int col = 16 * t + row;
-    for (int j = 0; j < 4; ++j) h2[(4 * q + j) * 64 + col] = to_bf16(fmaxf(acc[t][j] + bias[64 + col], 0.0f));
+    for (int j = 0; j < 4; ++j) h2[(4 * q + j) * 64 + col] = to_bf16(fmaxf(acc[t][j] + n.b2[t], 0.0f));
   }
-  __syncthreads();
+  wave_lds_sync();
   // layer 3: [16 x 64] x [64 x 16] (3 outputs used)
   f32x4 o = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int ks = 0; ks < 4; ++ks) {
-    bf16x4 a3, b;
-    for (int j = 0; j < 4; ++j) {
-      a3[j] = (short)h2[row * 64 + 16 * ks + 4 * q + j];
-      b[j] = (short)wb[1024 + 4096 + (16 * ks + 4 * q + j) * 16 + row];
-    }
-    o = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, b, o, 0, 0, 0);
+    bf16x4 a3;
+    for (int j = 0; j < 4; ++j) a3[j] = (short)h2[row * 64 + 16 * ks + 4 * q + j];
+    o = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, n.w3[ks], o, 0, 0, 0);
   }
   if (row < kMlpOut)
-    for (int j = 0; j < 4; ++j) y[(4 * q + j) * 4 + row] = o[j] + bias[128 + row];
-  __syncthreads();
+    for (int j = 0; j < 4; ++j) y[(4 * q + j) * 4 + row] = o[j] + n.b3;
+  wave_lds_sync();
 }
 
 struct InferLds {
   uint16_t wb[kMlpWb];
   float bias[kMlpBias];
-  uint16_t x[4][16 * 16];
   uint16_t h1[4][16 * 64];
   uint16_t h2[4][16 * 64];
   float y[4][16 * 4];
 };
 
+// the packed network into LDS (whole workgroup, then a barrier)
 __device__ void load_net(InferLds& s, const uint16_t* wb, const float* bias) {
   for (int i = threadIdx.x; i < kMlpWb; i += kInfBS) s.wb[i] = wb[i];
   for (int i = threadIdx.x; i < kMlpBias; i += kInfBS) s.bias[i] = bias[i];
+  __syncthreads();
+}
+
+// A operand of the first layer for row i of a [n][stride] float feature matrix
+__device__ __forceinline__ bf16x4 mlp_input(const float* X, int64_t stride, int i, int n) {
+  const int q = lane_id() >> 4;
+  bf16x4 a;
+  for (int j = 0; j < 4; ++j) {
+    const int k = 4 * q + j;
+    a[j] = (short)((i < n && k < kMlpIn) ? to_bf16(X[(int64_t)i * stride + k]) : 0);
+  }
+  return a;
 }
 
 // standalone inference: X [n][12] float -> Y [n][3] float
@@ -134,24 +168,20 @@ __global__ __launch_bounds__(kInfBS) void k_mlp_infer(const uint16_t* __restrict
                                                       const float* __restrict__ X, int n, float* __restrict__ Y) {
   __shared__ InferLds s;
   load_net(s, wb, bias);
-  __syncthreads();
   const int wv = threadIdx.x >> 6, l = lane_id();
   const int base = (blockIdx.x * 4 + wv) * 16;
-  for (int e = l; e < 256; e += 64) {
-    const int r = e >> 4, k = e & 15;
-    const int i = base + r;
-    s.x[wv][e] = (i < n && k < kMlpIn) ? to_bf16(X[(int64_t)i * kMlpIn + k]) : 0;
-  }
-  __syncthreads();
-  mlp_tile(s.wb, s.bias, s.x[wv], s.h1[wv], s.h2[wv], s.y[wv]);
+  MlpLane net;
+  mlp_lane_load(net, s.wb, s.bias);
+  mlp_rows(net, mlp_input(X, kMlpIn, base + (l & 15), n), s.h1[wv], s.h2[wv], s.y[wv]);
   if (l < 16 && base + l < n)
     for (int o = 0; o < kMlpOut; ++o) Y[(int64_t)(base + l) * kMlpOut + o] = s.y[wv][l * 4 + o];
 }
 
 // world: learned start of every contact copy (uid order in, slot order out).
-// A persistent grid: every workgroup loads the network into LDS once and then
-// takes tiles of 64 copies (16 per wave) with a grid stride.
-constexpr int kInfWorldBlocks = 2048;
+// A persistent grid: every workgroup stages the network in LDS once, each of
+// its waves takes the network into registers and then evaluates tiles of 16
+// copies with a grid stride, on its own (no workgroup barrier in the loop).
+constexpr int kInfWorldBlocks = 1024;
 
 __global__ __launch_bounds__(kInfBS) void k_mlp_world(WP w) {
   __shared__ InferLds s;
@@ -159,31 +189,29 @@ __global__ __launch_bounds__(kInfBS) void k_mlp_world(WP w) {
   const int M = min(w.part_copy_off[w.G], w.Mcap);
   if (blockIdx.x * 64 >= M) return;
   load_net(s, w.mlp_wb, w.mlp_bias);
-  __syncthreads();
   const int wv = threadIdx.x >> 6, l = lane_id();
-  for (int tile = blockIdx.x; tile * 64 < M; tile += gridDim.x) {
-    const int base = (tile * 4 + wv) * 16;
-    for (int e = l; e < 256; e += 64) {
-      const int r = e >> 4, k = e & 15;
-      const int u = base + r;
-      s.x[wv][e] = (u < M && k < kMlpIn) ? to_bf16(w.r_feat[(int64_t)u * kFeatStride + k]) : 0;
+  MlpLane net;
+  mlp_lane_load(net, s.wb, s.bias);
+  for (int tile = blockIdx.x * 4 + wv; tile * 16 < M; tile += gridDim.x * 4) {
+    const int base = tile * 16;
+    // the copy of lane l < 16: its slot and impulse scale, loaded ahead of the rows
+    int slot = -1;
+    float sc = 0.0f;
+    const int u = base + l;
+    if (l < 16 && u < M && w.cp_src[u] >= w.J) {
+      slot = w.cp_slot[u];
+      sc = w.r_feat[(int64_t)u * kFeatStride + 12];
     }
-    __syncthreads();
-    mlp_tile(s.wb, s.bias, s.x[wv], s.h1[wv], s.h2[wv], s.y[wv]);
-    if (l < 16) {
-      const int u = base + l;
-      if (u < M && w.cp_src[u] >= w.J) {
-        const int slot = w.cp_slot[u];
-        const float sc = w.r_feat[(int64_t)u * kFeatStride + 12];
-        const float mu = w.r_rec[w.Mcap + slot].w;
-        const float ln = fmaxf(s.y[wv][l * 4] * sc, 0.0f);
-        const float bnd = mu * ln;
-        const float l1 = fminf(fmaxf(s.y[wv][l * 4 + 1] * sc, -bnd), bnd);
-        const float l2 = fminf(fmaxf(s.y[wv][l * 4 + 2] * sc, -bnd), bnd);
-        w.r_lamL[slot] = make_float4(ln, l1, l2, 0.0f);
-      }
+    mlp_rows(net, mlp_input(w.r_feat, kFeatStride, base + (l & 15), M), s.h1[wv], s.h2[wv], s.y[wv]);
+    if (slot >= 0) {
+      const float mu = w.r_rec[w.Mcap + slot].w;
+      const float ln = fmaxf(s.y[wv][l * 4] * sc, 0.0f);
+      const float bnd = mu * ln;
+      const float l1 = fminf(fmaxf(s.y[wv][l * 4 + 1] * sc, -bnd), bnd);
+      const float l2 = fminf(fmaxf(s.y[wv][l * 4 + 2] * sc, -bnd), bnd);
+      w.r_lamL[slot] = make_float4(ln, l1, l2, 0.0f);
     }
-    __syncthreads();
+    wave_lds_sync();  // y is rewritten by the next tile
   }
 }
 
