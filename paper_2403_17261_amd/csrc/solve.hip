@@ -329,12 +329,21 @@ __global__ __launch_bounds__(BS) void k_colour(WP w, int split) {
         overflow = true;
         break;
       }
+      // the thread's copies whose higher-priority neighbours are all coloured:
+      // their counters read together rather than one after another
+      uint32_t ready = 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if ((todo >> j) & 1u) {
+          const int ul = tid + j * BS;
+          const uint32_t wv = wait_lds[ul >> 1] >> (16 * (ul & 1));
+          ready |= ((wv & 0xffffu) == 0 ? 1u : 0u) << j;
+        }
+      }
       uint32_t now = 0;
-      for (uint32_t t = todo; t; t &= t - 1) {
+      for (uint32_t t = ready; t; t &= t - 1) {
         const int j = __ffs(t) - 1;
         const int u = u0 + tid + j * BS;
-        const uint32_t wv = wait_lds[(u - u0) >> 1] >> (16 * ((u - u0) & 1));
-        if ((wv & 0xffffu) != 0) continue;
         uint64_t used = 0;
         const int ends[2] = {w.cp_ia[u], w.cp_ib[u]};
         for (int e = 0; e < 2; ++e) {
