@@ -33,6 +33,7 @@
 #include "ovl_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include "wave.h"
 
 // No implicit fused multiply-add in this file: every fused operation is written
@@ -83,6 +84,11 @@ __device__ __forceinline__ float tangents(f3 n, f3& t1, f3& t2) {
   tangents_from(n, a, t1, t2);
   return a;
 }
+
+// 1/A of a sphere contact's rows: the hardware reciprocal (within one ulp).
+// The row assembly stores it and the sphere-only sweeps form it again from
+// the replicas' inverse masses; both use this, so both give the same bits.
+__device__ __forceinline__ float row_rcp(float a) { return __builtin_amdgcn_rcpf(a); }
 
 __device__ __forceinline__ f3 quat_rotate(float qw, float qx, float qy, float qz, f3 v) {
   float nn = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -774,7 +780,7 @@ __global__ void k_rows(WP w) {
       const float At = ima + imb + iia * la * la + iib * lb * lb + w.cfm;
       w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
       w.r_rec[MC + slot] = make_float4(la, lb, bias, mu);
-      w.r_rec[2 * MC + slot] = make_float4(1.0f / An, 1.0f / At, An, At);
+      w.r_rec[2 * MC + slot] = make_float4(row_rcp(An), row_rcp(At), An, At);
       w.r_ids[slot] = make_int2(w.cp_ia[u], b >= 0 ? w.cp_ib[u] : -1);
     } else {
       // capsule contact: full lever arms, A_rr = m_a^-1 + m_b^-1 + sum (r x d).I^-1 (r x d)
@@ -903,14 +909,15 @@ __device__ __forceinline__ Slots slots_of(const WP& w, int s0) {
 // fetch_rec): `base` is the same in every lane, so its byte offset joins the
 // scalar bases, and toff = 16 tid is the lane's vector offset.  Lanes may read
 // up to a workgroup past the last slot: the record arrays are padded by
-// kSlotPad slots.
-template <bool kCaps>
+// kSlotPad slots.  kCompact (sphere contacts only) leaves out the third row
+// record (the row masses), which do_slot forms again from the replicas.
+template <bool kCaps, bool kCompact = false>
 __device__ __forceinline__ void fetch_lane(const Slots& S, int base, uint32_t toff, Rec& R, bool packed) {
   // one 32-bit vector offset from the partition's scalar bases for all the loads
   const uint32_t o = ((uint32_t)base << 4) + toff;
   R.r0 = *reinterpret_cast<const float4*>(S.r0 + o);
   R.r1 = *reinterpret_cast<const float4*>(S.r1 + o);
-  R.r2 = *reinterpret_cast<const float4*>(S.r2 + o);
+  if (!kCompact) R.r2 = *reinterpret_cast<const float4*>(S.r2 + o);
   if (!packed) R.id = *reinterpret_cast<const int2*>(S.ids + (o >> 1));
   R.lam = *reinterpret_cast<const float4*>(S.lam + o);
   if (kCaps) {
@@ -953,9 +960,10 @@ __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcp
 // the other rows' velocities unchanged.  Solving the rows in order n, t1, t2
 // therefore only needs the velocities before the contact, and the three
 // impulses are applied together.  `solve` false applies lam as given (warm
-// start) instead of projecting.
+// start) instead of projecting.  r2 = (1/A_n, 1/A_t, A_n, A_t).
 template <bool solve>
-__device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl) {
+__device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl,
+                                             const float4 r2) {
   const f3 n = mk(R.r0.x, R.r0.y, R.r0.z);
   f3 t1, t2;
   tangents_from(n, R.r0.w, t1, t2);
@@ -966,20 +974,20 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
     const f3 sw = madd(scale(B.w, lb), A.w, la);
     // normal
     const float un = fmaf(cfm, lam.x, dot(n, dv) + bias);
-    const float ln = fmaxf(fmaf(-un, R.r2.x, lam.x), 0.0f);
+    const float ln = fmaxf(fmaf(-un, r2.x, lam.x), 0.0f);
     d0 = ln - lam.x;
     lam.x = ln;
     // friction box of the new normal impulse
     const float hi = mu * ln;
     const float u1 = fmaf(cfm, lam.y, dot(t1, dv) - dot(t2, sw));
-    const float l1 = fminf(fmaxf(fmaf(-u1, R.r2.y, lam.y), -hi), hi);
+    const float l1 = fminf(fmaxf(fmaf(-u1, r2.y, lam.y), -hi), hi);
     d1 = l1 - lam.y;
     lam.y = l1;
     const float u2 = fmaf(cfm, lam.z, dot(t2, dv) + dot(t1, sw));
-    const float l2 = fminf(fmaxf(fmaf(-u2, R.r2.y, lam.z), -hi), hi);
+    const float l2 = fminf(fmaxf(fmaf(-u2, r2.y, lam.z), -hi), hi);
     d2 = l2 - lam.z;
     lam.z = l2;
-    rl = fmaxf(rl, fmaxf(fabsf(d0) * R.r2.z, fmaxf(fabsf(d1), fabsf(d2)) * R.r2.w));
+    rl = fmaxf(rl, fmaxf(fabsf(d0) * r2.z, fmaxf(fabsf(d1), fabsf(d2)) * r2.w));
   } else {
     d0 = lam.x;
     d1 = lam.y;
@@ -1114,7 +1122,11 @@ __device__ float4 g_zero_body[2];
 // the velocities are in LDS (kLds), from g_zero_body otherwise, so that the
 // arithmetic is the same in both and no lane branches on it before the store.
 // A zero body stays zero in LDS because a zero inverse mass adds only zeros.
-template <bool solve, bool kCaps = false, bool kSweep = false, bool kLds = false>
+// kCompact: every copy is a sphere contact and its record has no row masses;
+// they are formed from the replicas' inverse masses exactly as the row
+// assembly forms them (the same operations in the same order), so the bits
+// are those of the stored record.
+template <bool solve, bool kCaps = false, bool kSweep = false, bool kLds = false, bool kCompact = false>
 __device__ __forceinline__ float4 do_slot(const WP& w, Vel V, Rec& R, float& rl, int r0 = 0) {
   Bod A = ld_body(V, R.ia);
   Bod B;
@@ -1134,7 +1146,12 @@ __device__ __forceinline__ float4 do_slot(const WP& w, Vel V, Rec& R, float& rl,
   // The record's registers are only read (the new impulses go to L): a record
   // loaded one colour ahead then stays in the registers it was loaded into.
   float4 L = R.lam;
-  if (kCaps && R.gen) {
+  if (kCompact) {
+    const float la = R.r1.x, lb = R.r1.y;
+    const float An = A.im + B.im + w.cfm;
+    const float At = A.im + B.im + A.ii * la * la + B.ii * lb * lb + w.cfm;
+    contact_rows<solve>(R, A, B, w.cfm, L, rl, make_float4(row_rcp(An), row_rcp(At), An, At));
+  } else if (kCaps && R.gen) {
     const float4 axA = w.rep_ax[r0 + R.ia];
     const float4 axB = hasB ? w.rep_ax[r0 + R.ib] : float4{};
     if (R.joint)
@@ -1144,7 +1161,7 @@ __device__ __forceinline__ float4 do_slot(const WP& w, Vel V, Rec& R, float& rl,
   } else if (R.joint) {
     joint_rows<solve>(R, A, B, w.cfm, L, rl);
   } else {
-    contact_rows<solve>(R, A, B, w.cfm, L, rl);
+    contact_rows<solve>(R, A, B, w.cfm, L, rl, R.r2);
   }
   st_body(V, R.ia, A);
   if ((kSweep && kLds) || hasB) st_body(V, R.ib, B);
@@ -1296,43 +1313,43 @@ __device__ float start_residual(const WP& w, Vel V, int s0, int ncol, const int*
 // the same loads in every pass and the wait for `cur` can leave the new loads
 // in flight.  All record addresses are a scalar base plus the lane's offset
 // toff = 16 tid.  Ends with the workgroup barrier between colours.
-template <int BS, bool kCaps, bool kLds>
+template <int BS, bool kCaps, bool kLds, bool kCompact>
 __device__ __forceinline__ void colour_pass(const WP& w, Vel V, const Slots& S, int b0, int b1, int n0, int n1,
                                             bool prefetch, Rec& cur, bool& has_cur, Rec& nxt, bool& has_nxt,
                                             int first, float& rl, int r0, bool packed, uint32_t toff,
                                             int* over = nullptr, float tol = 0.0f) {
   const int tid = threadIdx.x;
   has_nxt = prefetch && n0 + tid < n1;
-  fetch_lane<kCaps>(S, n0, toff, nxt, packed);
+  fetch_lane<kCaps, kCompact>(S, n0, toff, nxt, packed);
   // the thread's second slot of a colour larger than the workgroup: loaded once
   // the first one is decoded, so that its loads run during the first one's rows
   const int k2 = b0 + first;
   const bool has2 = tid < b1 - k2;
   // Wait here for `cur` (loaded one colour ahead, before the loads just issued
   // for `nxt`), ahead of the second slot's loads: a wait placed after those
-  // would also hold back the prefetch.  (With separate record ids, 5 or 7
+  // would also hold back the prefetch.  (With separate record ids, 4, 5 or 7
   // loads per record, this waits for one prefetch load too.)
-  constexpr int kFetchLoads = kCaps ? 6 : 4;
+  constexpr int kFetchLoads = kCaps ? 6 : (kCompact ? 3 : 4);
   __builtin_amdgcn_s_waitcnt(kWaitVmem0 | kFetchLoads);
   decode<kCaps>(cur, packed);
   Rec R2;
-  if (has2) fetch_lane<kCaps>(S, k2, toff, R2, packed);
+  if (has2) fetch_lane<kCaps, kCompact>(S, k2, toff, R2, packed);
   // both slots' impulses are stored after both are solved, so that the wait for
   // the second slot's loads does not also wait for the first slot's store
   float4 Lc, L2;
-  if (has_cur) Lc = do_slot<true, kCaps, true, kLds>(w, V, cur, rl, r0);
+  if (has_cur) Lc = do_slot<true, kCaps, true, kLds, kCompact>(w, V, cur, rl, r0);
   if (has2) {
     decode<kCaps>(R2, packed);
-    L2 = do_slot<true, kCaps, true, kLds>(w, V, R2, rl, r0);
+    L2 = do_slot<true, kCaps, true, kLds, kCompact>(w, V, R2, rl, r0);
   }
   if (has_cur) store_lam(S.lam + (((uint32_t)b0 << 4) + toff), Lc);
   if (has2) store_lam(S.lam + (((uint32_t)k2 << 4) + toff), L2);
   for (int k = k2 + BS; k < b1; k += BS) {
     if (tid < b1 - k) {
       Rec R;
-      fetch_lane<kCaps>(S, k, toff, R, packed);
+      fetch_lane<kCaps, kCompact>(S, k, toff, R, packed);
       decode<kCaps>(R, packed);
-      store_lam(S.lam + (((uint32_t)k << 4) + toff), do_slot<true, kCaps, true, kLds>(w, V, R, rl, r0));
+      store_lam(S.lam + (((uint32_t)k << 4) + toff), do_slot<true, kCaps, true, kLds, kCompact>(w, V, R, rl, r0));
     }
   }
   // the last colour of an adaptive sweep: a wave with a residual above the
@@ -1397,77 +1414,86 @@ __device__ void solve_partition(const WP& w, int p, Vel V, int* coff, float* red
   const int cap = w.forced ? w.part_force_iters[p] : w.max_iters;
   int it = 0;
   float rho = 0.0f;
-  // With a single colour the next record would be the current one, read before
-  // its impulses are stored: then nothing is prefetched and every slot is
-  // loaded where it is solved.
-  const int first = ncol == 1 ? 0 : BS;
-  // colour offsets: lane k of cv0 holds coff[k], cv1 the last one; read with readlane
-  const int cv0 = coff[lane_id()];
-  const int cv1 = __builtin_amdgcn_readfirstlane(coff[kColStride - 1]);
-  auto co = [&](int k) { return k < 64 ? __builtin_amdgcn_readlane(cv0, k) : cv1; };
-  const Slots S = slots_of(w, s0);
-  // two record sets used in turn: one is solved while the next colour's first
-  // slot is loaded into the other, so no record is ever copied between them
-  Rec ra, rb;
-  bool ha = ncol > 1 && co(0) + tid < co(1), hb = false;
-  const uint32_t toff = (uint32_t)tid << 4;
-  if (ncol > 0) fetch_lane<kCaps>(S, co(0), toff, ra, packed);
-  // Nothing may still be in flight into the first set when the loop is entered:
-  // otherwise the wait placed before its first use would also hold back the
-  // next colour's prefetch in every pass.
-  __builtin_amdgcn_s_waitcnt(0);
-  if (ncol == 0) {
-    // no rows: every sweep is empty (a zero residual stops adaptive sweeps after one)
-    it = (!w.forced && w.adaptive) ? min(cap, 1) : max(cap, 0);
-  } else if (cap > 0) {
-    int c = 0;
-    rl = 0.0f;
-    // Adaptive sweeps stop once no slot's residual exceeds the tolerance: the
-    // last colour of sweep s marks over[s mod 3] if one does (three flags in
-    // turn, so that clearing the flag of sweep s + 2 after sweep s never races
-    // with a read or a mark).  The residual itself is reduced once, at the end.
-    const bool check = !w.forced && w.adaptive;
-    int k3 = 0;
-    // after colour c: the end of a sweep may stop
-    auto next_colour = [&]() {
-      if (++c < ncol) return false;
-      c = 0;
-      ++it;
-      bool stop = it >= cap;
-      if (check) {
-        stop = stop || over[k3] == 0;
-        if (tid == 0) over[k3 == 0 ? 2 : k3 - 1] = 0;
-        k3 = k3 == 2 ? 0 : k3 + 1;
-      }
-      if (stop) rho = block_max<BS>(rl, red);
+  // A world of spheres alone (no joints, no capsules) sweeps with three loads
+  // per record instead of four: the row masses are formed from the replicas.
+  auto sweeps = [&](auto compact) {
+    constexpr bool kCompact = decltype(compact)::value;
+    // With a single colour the next record would be the current one, read before
+    // its impulses are stored: then nothing is prefetched and every slot is
+    // loaded where it is solved.
+    const int first = ncol == 1 ? 0 : BS;
+    // colour offsets: lane k of cv0 holds coff[k], cv1 the last one; read with readlane
+    const int cv0 = coff[lane_id()];
+    const int cv1 = __builtin_amdgcn_readfirstlane(coff[kColStride - 1]);
+    auto co = [&](int k) { return k < 64 ? __builtin_amdgcn_readlane(cv0, k) : cv1; };
+    const Slots S = slots_of(w, s0);
+    // two record sets used in turn: one is solved while the next colour's first
+    // slot is loaded into the other, so no record is ever copied between them
+    Rec ra, rb;
+    bool ha = ncol > 1 && co(0) + tid < co(1), hb = false;
+    const uint32_t toff = (uint32_t)tid << 4;
+    if (ncol > 0) fetch_lane<kCaps, kCompact>(S, co(0), toff, ra, packed);
+    // Nothing may still be in flight into the first set when the loop is entered:
+    // otherwise the wait placed before its first use would also hold back the
+    // next colour's prefetch in every pass.
+    __builtin_amdgcn_s_waitcnt(0);
+    if (ncol == 0) {
+      // no rows: every sweep is empty (a zero residual stops adaptive sweeps after one)
+      it = (!w.forced && w.adaptive) ? min(cap, 1) : max(cap, 0);
+    } else if (cap > 0) {
+      int c = 0;
       rl = 0.0f;
-      return stop;
-    };
-    // [b0, b1): the current colour's slots, carried from the previous pass, so
-    // that a pass reads one new offset
-    const int co0 = co(0);
-    int b0 = co0, b1 = co(1);
-    for (;;) {
-      {
-        const int cn = c + 1 < ncol ? c + 1 : 0;
-        const int n0 = cn == 0 ? co0 : b1, n1 = co(cn + 1);
-        colour_pass<BS, kCaps, kLds>(w, V, S, b0, b1, n0, n1, ncol > 1, ra, ha, rb, hb, first, rl, r0, packed,
-                                     toff, check && c == ncol - 1 ? over + k3 : nullptr, w.tol);
-        b0 = n0;
-        b1 = n1;
+      // Adaptive sweeps stop once no slot's residual exceeds the tolerance: the
+      // last colour of sweep s marks over[s mod 3] if one does (three flags in
+      // turn, so that clearing the flag of sweep s + 2 after sweep s never races
+      // with a read or a mark).  The residual itself is reduced once, at the end.
+      const bool check = !w.forced && w.adaptive;
+      int k3 = 0;
+      // after colour c: the end of a sweep may stop
+      auto next_colour = [&]() {
+        if (++c < ncol) return false;
+        c = 0;
+        ++it;
+        bool stop = it >= cap;
+        if (check) {
+          stop = stop || over[k3] == 0;
+          if (tid == 0) over[k3 == 0 ? 2 : k3 - 1] = 0;
+          k3 = k3 == 2 ? 0 : k3 + 1;
+        }
+        if (stop) rho = block_max<BS>(rl, red);
+        rl = 0.0f;
+        return stop;
+      };
+      // [b0, b1): the current colour's slots, carried from the previous pass, so
+      // that a pass reads one new offset
+      const int co0 = co(0);
+      int b0 = co0, b1 = co(1);
+      for (;;) {
+        {
+          const int cn = c + 1 < ncol ? c + 1 : 0;
+          const int n0 = cn == 0 ? co0 : b1, n1 = co(cn + 1);
+          colour_pass<BS, kCaps, kLds, kCompact>(w, V, S, b0, b1, n0, n1, ncol > 1, ra, ha, rb, hb, first, rl, r0,
+                                                 packed, toff, check && c == ncol - 1 ? over + k3 : nullptr, w.tol);
+          b0 = n0;
+          b1 = n1;
+        }
+        if (next_colour()) break;
+        {
+          const int cn = c + 1 < ncol ? c + 1 : 0;
+          const int n0 = cn == 0 ? co0 : b1, n1 = co(cn + 1);
+          colour_pass<BS, kCaps, kLds, kCompact>(w, V, S, b0, b1, n0, n1, ncol > 1, rb, hb, ra, ha, first, rl, r0,
+                                                 packed, toff, check && c == ncol - 1 ? over + k3 : nullptr, w.tol);
+          b0 = n0;
+          b1 = n1;
+        }
+        if (next_colour()) break;
       }
-      if (next_colour()) break;
-      {
-        const int cn = c + 1 < ncol ? c + 1 : 0;
-        const int n0 = cn == 0 ? co0 : b1, n1 = co(cn + 1);
-        colour_pass<BS, kCaps, kLds>(w, V, S, b0, b1, n0, n1, ncol > 1, rb, hb, ra, ha, first, rl, r0, packed,
-                                     toff, check && c == ncol - 1 ? over + k3 : nullptr, w.tol);
-        b0 = n0;
-        b1 = n1;
-      }
-      if (next_colour()) break;
     }
-  }
+  };
+  if (!kCaps && w.J == 0)
+    sweeps(std::true_type{});
+  else
+    sweeps(std::false_type{});
   // integrate and write the replica states
   const float h = w.dt;
   bool bad = false;
