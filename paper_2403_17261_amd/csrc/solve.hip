@@ -90,6 +90,18 @@ __device__ __forceinline__ float tangents(f3 n, f3& t1, f3& t2) {
 // the replicas' inverse masses; both use this, so both give the same bits.
 __device__ __forceinline__ float row_rcp(float a) { return __builtin_amdgcn_rcpf(a); }
 
+// (1/A_n, 1/A_t, A_n, A_t) of a sphere contact between bodies of inverse
+// masses ima, imb and inverse inertias iia, iib, with lever arms la, lb
+// (lia = iia la, lib = iib lb): A_n = m_a^-1 + m_b^-1 + cfm and
+// A_t = A_n + l_a^2 I_a^-1 + l_b^2 I_b^-1.  The row assembly and the
+// sphere-only sweeps both call it, so both give the same bits.
+__device__ __forceinline__ float4 sphere_row_masses(float ima, float imb, float la, float lia, float lb, float lib,
+                                                    float cfm) {
+  const float An = ima + imb + cfm;
+  const float At = fmaf(la, lia, fmaf(lb, lib, An));
+  return make_float4(row_rcp(An), row_rcp(At), An, At);
+}
+
 __device__ __forceinline__ f3 quat_rotate(float qw, float qx, float qy, float qz, f3 v) {
   float nn = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= nn;
@@ -776,11 +788,9 @@ __global__ void k_rows(WP w) {
     const bool gen = w.has_caps && (w.b_half[a] > 0.0f || (b >= 0 && w.b_half[b] > 0.0f));
     if (!gen) {
       // sphere contact: r_a = l_a n, r_b = -l_b n, so r x n = 0 and |r x t|^2 = l^2
-      const float An = ima + imb + w.cfm;
-      const float At = ima + imb + iia * la * la + iib * lb * lb + w.cfm;
       w.r_rec[slot] = make_float4(n.x, n.y, n.z, ad);
       w.r_rec[MC + slot] = make_float4(la, lb, bias, mu);
-      w.r_rec[2 * MC + slot] = make_float4(row_rcp(An), row_rcp(At), An, At);
+      w.r_rec[2 * MC + slot] = sphere_row_masses(ima, imb, la, iia * la, lb, iib * lb, w.cfm);
       w.r_ids[slot] = make_int2(w.cp_ia[u], b >= 0 ? w.cp_ib[u] : -1);
     } else {
       // capsule contact: full lever arms, A_rr = m_a^-1 + m_b^-1 + sum (r x d).I^-1 (r x d)
@@ -960,30 +970,44 @@ __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcp
 // the other rows' velocities unchanged.  Solving the rows in order n, t1, t2
 // therefore only needs the velocities before the contact, and the three
 // impulses are applied together.  `solve` false applies lam as given (warm
-// start) instead of projecting.  r2 = (1/A_n, 1/A_t, A_n, A_t).
-template <bool solve>
+// start) instead of projecting.  r2 = (1/A_n, 1/A_t, A_n, A_t); kCompact forms
+// it here from the bodies' inverse masses instead (see sphere_row_masses).
+//
+// The tangents are never formed.  With s = sign(n_z), a the record's basis
+// coefficient and m = (a n_x, a n_y, -1), the basis of tangents_from is
+// t1 = e_x + s n_x m and t2 = s e_y + n_y m, so for any vector v
+//   n.v = h + n_z v_z,  t1.v = v_x + s n_x k,  t2.v = s v_y + n_y k,
+// with h = n_x v_x + n_y v_y and k = m.v = a h - v_z; and the impulse vectors
+//   P = n d0 + t1 d1 + t2 d2 = (n_x r + d1, n_y r + s d2, n_z d0 - c),
+//   Q = t2 d1 - t1 d2 = (a n_x e - d2, a n_y e + s d1, -e),
+// with c = s n_x d1 + n_y d2, r = d0 + a c and e = n_y d1 - s n_x d2.
+template <bool solve, bool kCompact = false>
 __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float cfm, float4& lam, float& rl,
-                                             const float4 r2) {
+                                             float4 r2) {
   const f3 n = mk(R.r0.x, R.r0.y, R.r0.z);
-  f3 t1, t2;
-  tangents_from(n, R.r0.w, t1, t2);
+  const float a = R.r0.w;
+  const float s = copysignf(1.0f, n.z), sx = s * n.x;
   const float la = R.r1.x, lb = R.r1.y, bias = R.r1.z, mu = R.r1.w;
+  const float lia = A.ii * la, lib = B.ii * lb;
+  if (kCompact) r2 = sphere_row_masses(A.im, B.im, la, lia, lb, lib, cfm);
   float d0, d1, d2;
   if (solve) {
     const f3 dv = sub(B.v, A.v);
     const f3 sw = madd(scale(B.w, lb), A.w, la);
+    const float h1 = fmaf(n.y, dv.y, n.x * dv.x), k1 = fmaf(a, h1, -dv.z);
+    const float h2 = fmaf(n.y, sw.y, n.x * sw.x), k2 = fmaf(a, h2, -sw.z);
     // normal
-    const float un = fmaf(cfm, lam.x, dot(n, dv) + bias);
+    const float un = fmaf(cfm, lam.x, fmaf(n.z, dv.z, h1) + bias);
     const float ln = fmaxf(fmaf(-un, r2.x, lam.x), 0.0f);
     d0 = ln - lam.x;
     lam.x = ln;
     // friction box of the new normal impulse
     const float hi = mu * ln;
-    const float u1 = fmaf(cfm, lam.y, dot(t1, dv) - dot(t2, sw));
+    const float u1 = fmaf(cfm, lam.y, fmaf(sx, k1, dv.x) - fmaf(n.y, k2, s * sw.y));
     const float l1 = fminf(fmaxf(fmaf(-u1, r2.y, lam.y), -hi), hi);
     d1 = l1 - lam.y;
     lam.y = l1;
-    const float u2 = fmaf(cfm, lam.z, dot(t2, dv) + dot(t1, sw));
+    const float u2 = fmaf(cfm, lam.z, fmaf(n.y, k1, s * dv.y) + fmaf(sx, k2, sw.x));
     const float l2 = fminf(fmaxf(fmaf(-u2, r2.y, lam.z), -hi), hi);
     d2 = l2 - lam.z;
     lam.z = l2;
@@ -993,12 +1017,14 @@ __device__ __forceinline__ void contact_rows(const Rec& R, Bod& A, Bod& B, float
     d1 = lam.y;
     d2 = lam.z;
   }
-  const f3 P = madd(madd(scale(n, d0), t1, d1), t2, d2);
-  const f3 Q = msub(scale(t2, d1), t1, d2);
+  const float c = fmaf(n.y, d2, sx * d1), r = fmaf(a, c, d0);
+  const float e = fmaf(n.y, d1, -(sx * d2)), ae = a * e;
+  const f3 P = mk(fmaf(n.x, r, d1), fmaf(n.y, r, s * d2), fmaf(n.z, d0, -c));
+  const f3 Q = mk(fmaf(n.x, ae, -d2), fmaf(n.y, ae, s * d1), -e);
   A.v = msub(A.v, P, A.im);
   B.v = madd(B.v, P, B.im);
-  A.w = msub(A.w, Q, A.ii * la);
-  B.w = msub(B.w, Q, B.ii * lb);
+  A.w = msub(A.w, Q, lia);
+  B.w = msub(B.w, Q, lib);
 }
 
 // Ball joint, rows along -e_k: J_k v = (v_a + w_a x r_a - v_b - w_b x r_b)_k;
@@ -1147,10 +1173,7 @@ __device__ __forceinline__ float4 do_slot(const WP& w, Vel V, Rec& R, float& rl,
   // loaded one colour ahead then stays in the registers it was loaded into.
   float4 L = R.lam;
   if (kCompact) {
-    const float la = R.r1.x, lb = R.r1.y;
-    const float An = A.im + B.im + w.cfm;
-    const float At = A.im + B.im + A.ii * la * la + B.ii * lb * lb + w.cfm;
-    contact_rows<solve>(R, A, B, w.cfm, L, rl, make_float4(row_rcp(An), row_rcp(At), An, At));
+    contact_rows<solve, true>(R, A, B, w.cfm, L, rl, float4{});
   } else if (kCaps && R.gen) {
     const float4 axA = w.rep_ax[r0 + R.ia];
     const float4 axB = hasB ? w.rep_ax[r0 + R.ib] : float4{};
